@@ -1,0 +1,253 @@
+"""Pins of the full oracle sweep / split step against what the mathematics
+fixes: exact preservation of uniform and static-dipole states, conservation
+on periodic boxes, symmetries, linear MHD eigenmode convergence, and the
+exact gas-dynamic solution in the B = 0 limit.
+
+Paper: Section II (conservative ideal MHD with B = B_d + B', zone-centred
+averages, parabolic reconstruction, Lagrangian update + remap) and the
+dimensional splitting of Section III-A.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import exact_riemann as X
+from paper_1607_02214_amd import inputs as I
+
+import oracle_cases as OC
+
+G = 5.0 / 3.0
+
+
+def _rng_faces(rng, n, lo, hi):
+    w = rng.uniform(lo, hi, n)
+    return np.concatenate([[0.0], np.cumsum(w)])
+
+
+# ------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("v", [(0.0, 0.0, 0.0), (0.7, -1.3, 0.4)])
+def test_uniform_state_preserved_bitwise_on_stretched_periodic_grid(v):
+    rng = np.random.default_rng(42)
+    faces = [_rng_faces(rng, n, 0.05, 0.3) for n in (12, 9, 10)]
+    U0 = I.uniform_state((10, 9, 12), rho=1.3, v=v, B=(0.4, -0.9, 0.25), p=0.8)
+    prob = O.OracleProblem(faces)
+    dt = 0.5 * prob.cfl_dt(U0, 0.8)
+    st = O.Stats()
+    U = U0
+    for s in range(3):
+        U = prob.step(U, dt, s, st)
+    assert np.array_equal(U, U0)
+    assert st.floor_hits == 0 and st.nonconverged == 0 and st.iters_hist[0] > 0
+    assert sum(st.iters_hist[1:]) == 0
+
+
+def test_static_dipole_equilibrium_preserved_bitwise():
+    faces = [I.stretched_faces(14, 10, w_min=0.5, core=4), I.stretched_faces(9, 9, w_min=0.5, core=4),
+             I.stretched_faces(8, 9, w_min=0.5, core=4)]
+    shape = tuple(len(f) - 1 for f in faces[::-1])
+    U0 = I.uniform_state(shape, rho=5.0, p=8.7)
+    prob = O.OracleProblem(faces, bc_lo=(1, 1, 1), bc_hi=(1, 1, 1), dip_moment=I.DIPOLE_MOMENT,
+                           dip_dir=I.DIPOLE_DIR, r_inner=3.0, inner_rho=5.0, inner_p=8.7)
+    dt = prob.cfl_dt(U0, 0.4)
+    assert dt > 0
+    U = U0
+    for s in range(2):
+        U = prob.step(U, dt, s)
+    assert np.array_equal(U, U0)
+
+
+def test_conservation_on_periodic_box():
+    U0, faces = I.c1_state(n=16)
+    prob = O.OracleProblem(faces)
+    tot0 = prob.totals(U0)
+    st = O.Stats()
+    U = U0
+    for s in range(20):
+        dt = prob.cfl_dt(U, 0.4)
+        U = prob.step(U, dt, s, st)
+    tot = prob.totals(U)
+    assert st.floor_hits == 0 and st.nonconverged == 0 and st.nonphys == 0
+    # mass, momentum, energy conserved to roundoff (B' is not: -v div B' source)
+    for q in (0, 1, 2, 3, 7):
+        scale = max(abs(tot0[q]), np.sum(np.abs(U0[q])) / U0[q].size)
+        assert abs(tot[q] - tot0[q]) <= 1e-13 * scale, (q, tot[q], tot0[q])
+    # and the state did change
+    assert np.max(np.abs(U - U0)) > 1e-6
+
+
+def test_axis_permutation_is_bitwise():
+    rng = np.random.default_rng(5)
+    faces = [_rng_faces(rng, n, 0.05, 0.2) for n in (11, 9, 10)]
+    U = I.random_smooth_state((10, 9, 11), seed=3)
+    prob = O.OracleProblem(faces)
+    dt = prob.cfl_dt(U, 0.4)
+    # cyclic relabelling x->y->z->x of axes and vector components
+    Up = np.transpose(U, (0, 2, 3, 1)).copy()
+    comp = [0, 3, 1, 2, 6, 4, 5, 7]          # new (x,y,z) = old (z,x,y)
+    Up = Up[comp].copy()
+    probp = O.OracleProblem([faces[2], faces[0], faces[1]])
+    for a in range(3):
+        r = prob.sweep(U, dt, a)
+        rp = probp.sweep(Up, dt, (a + 1) % 3)
+        back = np.transpose(rp[[0, 2, 3, 1, 5, 6, 4, 7]], (0, 3, 1, 2))
+        assert np.array_equal(back, r), a
+
+
+def test_transverse_mirror_is_bitwise_and_normal_mirror_to_roundoff():
+    rng = np.random.default_rng(8)
+    faces = [_rng_faces(rng, n, 0.05, 0.2) for n in (12, 10, 9)]
+    U = I.random_smooth_state((9, 10, 12), seed=11)
+    prob = O.OracleProblem(faces)
+    dt = prob.cfl_dt(U, 0.4)
+    r = prob.sweep(U, dt, 0)
+    # reflect y (transverse to the x sweep): flip the y index, negate v_y, B_y
+    fy = faces[1]
+    probm = O.OracleProblem([faces[0], (fy[-1] + fy[0] - fy)[::-1].copy(), faces[2]])
+    Um = U[:, :, ::-1, :].copy()
+    Um[2] *= -1
+    Um[5] *= -1
+    rm = probm.sweep(Um, dt, 0)
+    rm = rm[:, :, ::-1, :]
+    rm[2] *= -1
+    rm[5] *= -1
+    assert np.array_equal(rm, r)
+    # reflect x (the sweep direction): equal to roundoff
+    fx = faces[0]
+    probx = O.OracleProblem([(fx[-1] + fx[0] - fx)[::-1].copy(), faces[1], faces[2]])
+    Ux = U[:, :, :, ::-1].copy()
+    Ux[1] *= -1
+    Ux[4] *= -1
+    rx = probx.sweep(Ux, dt, 0)[:, :, :, ::-1].copy()
+    rx[1] *= -1
+    rx[4] *= -1
+    scale = np.max(np.abs(U), axis=(1, 2, 3))[:, None, None, None]
+    assert np.max(np.abs(rx - r) / scale) < 1e-13
+
+
+# ---------------------------------------------------------- convergence
+
+@pytest.mark.parametrize("kind", ["fast", "alfven", "slow"])
+def test_linear_eigenmodes_along_axis_converge_second_order(kind):
+    errs = []
+    for N in (32, 64, 128):
+        U0, faces, lam = OC.wave_state_1d(N, kind, B=(1.0, 1.2, 0.9))
+        prob = O.OracleProblem(faces)
+        U, _ = OC.run_to(prob, U0, 1.0 / lam)
+        errs.append(np.sum(np.abs(U - U0)) / N)
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders >= 1.8), orders
+
+
+@pytest.mark.parametrize("kind", ["fast", "alfven", "slow"])
+def test_oblique_eigenmodes_converge_second_order(kind):
+    # wave vector along (1,1,0): each split sweep sees a non-eigen mixture
+    # and a normal field that varies along its pencils
+    errs = []
+    for N in (16, 32, 64):
+        U0, faces, lam, T = OC.oblique_wave_state(N, kind)
+        prob = O.OracleProblem(faces)
+        U, _ = OC.run_to(prob, U0, T)
+        errs.append(np.sum(np.abs(U - U0)) / N ** 2)
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.mean(orders) >= 1.8 and orders[-1] >= 1.7, orders
+
+
+def test_sod_shock_tube_converges_to_exact_solution():
+    errs = []
+    for N in (100, 200, 400):
+        f = I.uniform_faces(N)
+        xc = I.centres(f)
+        z = 0 * xc
+        rho = np.where(xc < 0.5, 1.0, 0.125)
+        p = np.where(xc < 0.5, 1.0, 0.1)
+        U0 = I.conserved(rho, z, z, z, z, z, z, p).reshape(8, 1, 1, N)
+        prob = O.OracleProblem([f, I.uniform_faces(1), I.uniform_faces(1)], bc_lo=(1, 0, 0), bc_hi=(1, 0, 0))
+        U, _ = OC.run_to(prob, U0, 0.2)
+        ex = np.array([X.sample((x - 0.5) / 0.2, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1) for x in xc])
+        errs.append(np.sum(np.abs(U[0, 0, 0] - ex[:, 0])) / N)
+    errs = np.array(errs)
+    assert errs[0] < 8e-3
+    orders = np.log2(errs[:-1] / errs[1:])
+    assert np.all(orders > 0.8), orders
+
+
+def test_colliding_streams_plateau_matches_exact_star_state():
+    N = 200
+    f = I.uniform_faces(N)
+    xc = I.centres(f)
+    z = 0 * xc
+    u = np.where(xc < 0.5, 1.0, -1.0)
+    U0 = I.conserved(1.0 + z, u, z, z, z, z, z, 1.0 + z).reshape(8, 1, 1, N)
+    prob = O.OracleProblem([f, I.uniform_faces(1), I.uniform_faces(1)], bc_lo=(1, 0, 0), bc_hi=(1, 0, 0))
+    U, _ = OC.run_to(prob, U0, 0.15)
+    ps, us = X.star_state(1.0, 1.0, 1.0, 1.0, -1.0, 1.0, gamma=G)
+    mid = slice(N // 2 - 10, N // 2 + 10)
+    rho = U[0, 0, 0, mid]
+    m = U[1, 0, 0, mid]
+    p = (G - 1) * (U[7, 0, 0, mid] - 0.5 * m * m / rho)
+    assert np.max(np.abs(m / rho)) < 1e-3
+    assert np.max(np.abs(p - ps)) / ps < 2e-2
+
+
+# ------------------------------------------------------------ diagnostics
+
+def test_counters_report_floor_nonconvergence_and_nonphysical_zones():
+    N = 40
+    f = I.uniform_faces(N)
+    xc = I.centres(f)
+    z = 0 * xc
+    faces = [f, I.uniform_faces(1), I.uniform_faces(1)]
+    # strong jump + max_iter = 1 -> non-converged faces
+    U0 = I.conserved(np.where(xc < 0.5, 1.0, 0.01), np.where(xc < 0.5, 5.0, -5.0), z, z, z, z, z,
+                     np.where(xc < 0.5, 100.0, 0.01)).reshape(8, 1, 1, N)
+    prob = O.OracleProblem(faces, bc_lo=(1, 0, 0), bc_hi=(1, 0, 0), max_iter=1, tol=1e-14)
+    st = O.Stats()
+    prob.sweep(U0, 0.3 * prob.cfl_dt(U0, 1.0), 0, st)
+    assert st.nonconverged > 0
+    # negative internal energy -> floor hit
+    U1 = I.uniform_state((1, 1, N))
+    U1[7, 0, 0, 10] = 0.1 * U1[7, 0, 0, 10] - 5.0
+    st = O.Stats()
+    prob = O.OracleProblem(faces)
+    prob.sweep(U1, 1e-3, 0, st)
+    assert st.floor_hits >= 1
+    # non-positive density -> nonphysical
+    U2 = I.uniform_state((1, 1, N))
+    U2[0, 0, 0, 7] = -1.0
+    st = O.Stats()
+    prob.sweep(U2, 1e-3, 0, st)
+    assert st.nonphys >= 1
+
+
+def test_dipole_field_is_solenoidal_and_irrotational():
+    prob = O.OracleProblem([I.uniform_faces(1)] * 3, dip_moment=I.DIPOLE_MOMENT, dip_dir=I.DIPOLE_DIR)
+    r = np.array([4.3, -2.2, 3.1])
+    h = 1e-4
+    J = np.zeros((3, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        J[:, k] = (prob.dipole(r + e) - prob.dipole(r - e)) / (2 * h)
+    scale = np.max(np.abs(J))
+    assert abs(np.trace(J)) < 1e-7 * scale
+    assert np.max(np.abs(J - J.T)) < 1e-7 * scale
+    # equatorial field points north with magnitude M / r^3
+    B = prob.dipole(np.array([5.0, 0.0, 0.0]))
+    assert abs(B[2] - I.DIPOLE_MOMENT / 125.0) < 1e-12 * B[2] and abs(B[0]) < 1e-12
+
+
+def test_rejects_bad_arguments():
+    f = I.uniform_faces(8)
+    prob = O.OracleProblem([f, f, f])
+    U = I.uniform_state((8, 8, 8))
+    with pytest.raises(ValueError):
+        prob.sweep(U, 1e-3, 3)
+    with pytest.raises(ValueError):
+        prob.sweep(U, -1.0, 0)
+    bad = f.copy()
+    bad[3] = bad[2]
+    with pytest.raises(ValueError):
+        O.OracleProblem([bad, f, f]).sweep(U, 1e-3, 0)
