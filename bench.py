@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the split PPMLR-MHD step on one MI355X.
+
+Workload (the inflow/dipole run of the paper's Section IV-A set-up at the
+configured size): 256 x 192 x 192 stretched Cartesian grid (cell sizes
+0.25 .. 2 R_E, growth 1.03), solar wind n = 5 cm^-3, v = 400 km/s,
+T = 1e5 K, IMF Bz = -5 nT entering at x_max, dipole of moment 8e15 T m^3,
+fixed inner boundary r < 3 R_E, FP32 state with FP64 dt reduction.  One step
+= dt from the fused signal-speed maximum + x, y, z sweeps (z, y, x on odd
+steps); the state stays resident in HBM.
+
+Prints one JSON line: zone-updates/s (zones x steps / wall time), the
+roofline of the dominant sweep kernel (algorithmic bytes: 8 conserved
+variables read and written once per sweep), and the FP64 CPU oracle timed on
+a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_1607_02214_amd/csrc/ppmlr_sweep.hpp", "paper_1607_02214_amd/csrc/ppmlr_lib.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(dtype: str):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, valid only for the kernel source it was taken from."""
+    path = os.path.join(PROFILES, f"traffic_sweep_inflow_dipole_{dtype}.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None, d.get("source_hash")
+    return d, d.get("source_hash")
+
+
+def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
+    """FP64 oracle on a bounded sample of pencils of the same state (all three
+    sweep directions, equal pencil counts), timed on the host cores."""
+    import numpy as np
+    from oracle import oracle as O
+
+    prob = O.OracleProblem(setup.faces, bc_lo=setup.bc_lo, bc_hi=setup.bc_hi, dip_moment=setup.moment,
+                           dip_dir=setup.direction, inflow=setup.inflow, r_inner=setup.r_inner,
+                           inner_rho=setup.inner_rho, inner_p=setup.inner_p, p_floor=setup.p_floor)
+    rng = np.random.default_rng(seed)
+    n = [len(f) - 1 for f in setup.faces]
+    U = setup.U
+
+    def sample(npen):
+        zs = 0
+        t0 = time.perf_counter()
+        for axis in range(3):
+            n1, n2 = n[(axis + 1) % 3], n[(axis + 2) % 3]
+            j1 = rng.integers(0, n1, npen)
+            j2 = rng.integers(0, n2, npen)
+            prob.sweep_pencils(U, dt, axis, j1, j2)
+            zs += npen * n[axis]
+        return zs, time.perf_counter() - t0
+
+    zs, el = sample(32)                      # calibration
+    rate = zs / el
+    npen = max(32, int(seconds_target * rate / (sum(n))))
+    zs, el = sample(npen)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": zs / el / 3.0,
+        "unit": "zone-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{npen} random pencils per sweep direction of the 256x192x192 inflow-dipole start state "
+                  f"({zs} zone-sweeps, {el:.1f} s, FP64, OpenMP over pencils); zone-updates = zone-sweeps / 3",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cfl", type=float, default=0.4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the sweep path is single-device "
+              "(no halo exchange or collectives are built); use --gpus 1", file=sys.stderr)
+        sys.exit(3)
+
+    import numpy as np
+    import torch
+
+    from paper_1607_02214_amd import inputs as I
+    from paper_1607_02214_amd import ppmlr
+
+    setup = I.c2_setup()
+    nx, ny, nz = (len(f) - 1 for f in setup.faces)
+    zones = nx * ny * nz
+    print(f"[bench] grid {nx}x{ny}x{nz} = {zones} zones, building state", file=sys.stderr, flush=True)
+
+    def make_ctx():
+        ctx = ppmlr.Context(setup.faces, setup.bc_lo, setup.bc_hi, r_inner=setup.r_inner, p_floor=setup.p_floor)
+        ctx.set_dipole(setup.moment, setup.direction)
+        ctx.set_inflow(setup.inflow)
+        ctx.set_inner(setup.inner_rho, setup.inner_p)
+        return ctx
+
+    def run(dtype, steps, warmup, profile=True):
+        ctx = make_ctx()
+        u = torch.from_numpy(setup.U).to(device="cuda", dtype=dtype).contiguous()
+        ctx.advance(u, warmup, args.cfl)
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        ctx.set_profiling(profile)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        ctx.advance(u, steps, args.cfl)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        kms, kn = ctx.kernel_times()
+        status = ctx.status_check()
+        st = ctx.stats()
+        finite = bool(torch.isfinite(u).all().item())
+        return ctx, u, ms, wall, kms, kn, status, st, finite
+
+    print(f"[bench] fp32: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
+    ctx, u, ms, wall, kms, kn, status, st, finite = run(torch.float32, args.steps, args.warmup)
+    value = zones * args.steps / (ms / 1000.0)
+    avg = [kms[a] / kn[a] if kn[a] else 0.0 for a in range(3)]
+    dom = int(np.argmax(avg))
+    bytes_per_launch = 64.0 * zones            # 8 FP32 variables read + written
+    achieved = bytes_per_launch / (avg[dom] / 1000.0) / 1e9
+    traffic, _ = load_traffic("f32")
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic["bytes_per_launch"][str(dom)] if traffic else None,
+        "kernel": f"sweep axis {'xyz'[dom]} (f32)",
+        "avg_launch_ms": [round(a, 4) for a in avg],
+        "launches": kn,
+        "sum_kernel_ms_per_step": round(sum(kms) / args.steps, 4),
+    }
+    out = {
+        "metric": "zone-updates/s per 3D split step (FP32/learned vs FP64 plain) at stated error; HBM GB/s",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "inflow-dipole stretched grid 256x192x192, FP32 sweeps + FP64 dt, device-resident dt loop",
+            "grid": [nx, ny, nz],
+            "cfl": args.cfl,
+            "tiles": [ctx.get_tile(a, ppmlr.F32) for a in range(3)],
+        },
+        "roofline": roofline,
+        "health": {"status": status, "finite": finite, "floor_hits": st["floor_hits"],
+                   "nonconverged": st["nonconverged"], "simulated_time": ctx.time(u)},
+    }
+    del u
+    torch.cuda.empty_cache()
+
+    if not args.no_fp64:
+        n64 = max(5, min(20, args.steps))
+        print(f"[bench] fp64 plain: {n64} steps", file=sys.stderr, flush=True)
+        ctx64, u64, ms64, _, kms64, kn64, status64, _, fin64 = run(torch.float64, n64, 2)
+        v64 = zones * n64 / (ms64 / 1000.0)
+        avg64 = [kms64[a] / kn64[a] if kn64[a] else 0.0 for a in range(3)]
+        d64 = int(np.argmax(avg64))
+        ach64 = 128.0 * zones / (avg64[d64] / 1000.0) / 1e9
+        out["fp64_plain"] = {"value": v64, "steps": n64, "ms_per_step": ms64 / n64,
+                             "roofline_frac": round(ach64 / HBM_PEAK_GBS, 4), "status": status64,
+                             "finite": fin64, "fp32_speedup": value / v64}
+        del u64
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        prob = O.OracleProblem(setup.faces, bc_lo=setup.bc_lo, bc_hi=setup.bc_hi, dip_moment=setup.moment,
+                               dip_dir=setup.direction, r_inner=setup.r_inner)
+        dt = prob.cfl_dt(setup.U, args.cfl)
+        print(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(setup, dt, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,837 @@
+// ppmlr_lib.hip -- host side of the C ABI declared in include/ppmlr.h:
+// context and grid tables, kernel launches for sweeps and split steps, the
+// CFL reduction, deterministic totals, counters and the device-resident
+// time-step loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ppmlr.h"
+#include "ppmlr_sweep.hpp"
+
+using ppmlr::kG;
+using ppmlr::kSlotsA;
+using ppmlr::kSlotsB;
+using ppmlr::kStatWords;
+
+struct AxisTables {
+    // FP64 and FP32 copies: extended widths [M], centres [M], faces [M+1];
+    // interior widths and centres [n]
+    double *dx64 = nullptr, *xc64 = nullptr, *xf64 = nullptr, *dxi64 = nullptr, *xci64 = nullptr;
+    float *dx32 = nullptr, *xc32 = nullptr, *xf32 = nullptr, *dxi32 = nullptr, *xci32 = nullptr;
+};
+
+struct ppmlr_ctx {
+    int n[3];
+    int bc_lo[3], bc_hi[3];
+    double r_inner = 0.0;
+    double gamma = 5.0 / 3.0;
+    ppmlr_options opt;
+    std::vector<double> faces[3];
+    std::vector<double> ext_dx[3], ext_xc[3], ext_xf[3];
+    AxisTables tab[3];
+    double dip_m = 0.0, dir[3] = {0.0, 0.0, -1.0}, bext[3] = {0.0, 0.0, 0.0};
+    double inflow[8] = {1, 0, 0, 0, 0, 0, 0, 1};
+    double inner_rho = 1.0, inner_p = 1.0;
+    unsigned long long *d_stats = nullptr;   // kStatWords
+    unsigned long long *d_cflmax = nullptr;  // signal-speed max (double bits)
+    double *d_dt = nullptr;                  // device-resident dt
+    double *d_time = nullptr;                // accumulated simulated time
+    double *d_partials = nullptr;            // totals partial sums
+    int partial_blocks = 0;
+    long long step = 0;
+    int tile[3] = {0, 0, 0};
+    int device = 0;
+    std::string err;
+    // profiling: event pairs around sweep launches
+    bool profiling = false;
+    struct Mark { hipEvent_t start, stop; int axis; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+constexpr int kTotBlocks = 1024;  // fixed block count of the totals reduction
+
+ppmlr_status fail(ppmlr_ctx *c, ppmlr_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+ppmlr_status hip_check(ppmlr_ctx *c, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return PPMLR_OK;
+    return fail(c, e == hipErrorOutOfMemory ? PPMLR_ENOMEM : PPMLR_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+ppmlr_status upload(ppmlr_ctx *c, T **dst, const std::vector<double> &src)
+{
+    std::vector<T> tmp(src.begin(), src.end());
+    ppmlr_status s = hip_check(c, hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(tmp.size(), 1)), "hipMalloc");
+    if (s) return s;
+    return hip_check(c, hipMemcpy(*dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+// Extended geometry of one axis: ghost widths wrap on periodic axes and are
+// mirrored otherwise; ghost faces continue from the domain faces.
+void extend_axis(ppmlr_ctx *c, int a)
+{
+    const int N = c->n[a], M = N + 2 * kG;
+    const std::vector<double> &f = c->faces[a];
+    std::vector<double> &dx = c->ext_dx[a], &xc = c->ext_xc[a], &xf = c->ext_xf[a];
+    dx.assign(M, 0.0);
+    xc.assign(M, 0.0);
+    xf.assign(M + 1, 0.0);
+    auto width = [&](int k) { return f[k + 1] - f[k]; };
+    for (int i = 0; i < M; ++i) {
+        int gi = i - kG;
+        if (gi >= 0 && gi < N) {
+            dx[i] = width(gi);
+        } else if (gi < 0) {
+            if (c->bc_lo[a] == PPMLR_PERIODIC) dx[i] = width(((gi % N) + N) % N);
+            else dx[i] = width(std::min(-gi - 1, N - 1));
+        } else {
+            if (c->bc_hi[a] == PPMLR_PERIODIC) dx[i] = width(gi % N);
+            else dx[i] = width(std::max(2 * N - 1 - gi, 0));
+        }
+    }
+    for (int k = 0; k <= N; ++k) xf[kG + k] = f[k];
+    for (int i = kG + N; i < M; ++i) xf[i + 1] = xf[i] + dx[i];
+    for (int i = kG - 1; i >= 0; --i) xf[i] = xf[i + 1] - dx[i];
+    for (int i = 0; i < M; ++i) xc[i] = 0.5 * (xf[i] + xf[i + 1]);
+}
+
+void free_tables(ppmlr_ctx *c)
+{
+    for (int a = 0; a < 3; ++a) {
+        AxisTables &t = c->tab[a];
+        void *ptrs[] = {t.dx64, t.xc64, t.xf64, t.dxi64, t.xci64, t.dx32, t.xc32, t.xf32, t.dxi32, t.xci32};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        t = AxisTables();
+    }
+    void *more[] = {c->d_stats, c->d_cflmax, c->d_dt, c->d_time, c->d_partials};
+    for (void *p : more)
+        if (p) (void)hipFree(p);
+    c->d_stats = nullptr;
+    c->d_cflmax = nullptr;
+    c->d_dt = nullptr;
+    c->d_time = nullptr;
+    c->d_partials = nullptr;
+}
+
+bool has_background(const ppmlr_ctx *c)
+{
+    return c->dip_m != 0.0 || c->bext[0] != 0.0 || c->bext[1] != 0.0 || c->bext[2] != 0.0;
+}
+
+// Threads needed for a tile of P pencils, rounded to whole waves.
+int block_threads(int P, int M) { return ((P * M + 63) / 64) * 64; }
+
+// Automatic tile: the number of pencils per workgroup that wastes the fewest
+// lanes (padding to whole waves plus ghost zones), within the thread budget.
+int auto_tile(const ppmlr_ctx *c, int axis, int elem)
+{
+    const int N = c->n[axis], M = N + 2 * kG;
+    const int cap = (elem == 8) ? 512 : 1024;
+    const int nq = (axis == 0) ? c->n[1] : c->n[0];
+    int best = 1;
+    double best_cost = 1e30;
+    for (int P = 1; P <= 16; ++P) {
+        int thr = block_threads(P, M);
+        if (thr > cap && P > 1) break;
+        size_t lds = (size_t)(kSlotsA + kSlotsB) * P * M * elem;
+        if (lds > 160 * 1024) break;
+        int tiles_q = (nq + P - 1) / P;
+        double cost = (double)thr * tiles_q / ((double)N * nq);  // lanes per useful zone
+        if (cost < best_cost - 1e-9) { best_cost = cost; best = P; }
+    }
+    return best;
+}
+
+int pick_tile(const ppmlr_ctx *c, int axis, int elem)
+{
+    return c->tile[axis] > 0 ? c->tile[axis] : auto_tile(c, axis, elem);
+}
+
+template <typename T>
+void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, double dt, const double *dt_dev, int P)
+{
+    const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    const int N = c->n[axis], M = N + 2 * kG;
+    const bool f64 = sizeof(T) == 8;
+    auto tabs = [&](int ax, const T *&dx, const T *&xc, const T *&xf, const T *&dxi, const T *&xci) {
+        const AxisTables &t = c->tab[ax];
+        if (f64) {
+            dx = (const T *)t.dx64; xc = (const T *)t.xc64; xf = (const T *)t.xf64;
+            dxi = (const T *)t.dxi64; xci = (const T *)t.xci64;
+        } else {
+            dx = (const T *)t.dx32; xc = (const T *)t.xc32; xf = (const T *)t.xf32;
+            dxi = (const T *)t.dxi32; xci = (const T *)t.xci32;
+        }
+    };
+    std::memset(&a, 0, sizeof(a));
+    a.u = u;
+    a.vol = (long long)nx * ny * nz;
+    a.N = N;
+    a.M = M;
+    a.P = P;
+    a.S = P * M;
+    int qax, rax;
+    if (axis == 0) { a.stride_n = 1; a.stride_q = nx; a.stride_r = (long long)nx * ny; qax = 1; rax = 2; }
+    else if (axis == 1) { a.stride_n = nx; a.stride_q = 1; a.stride_r = (long long)nx * ny; qax = 0; rax = 2; }
+    else { a.stride_n = (long long)nx * ny; a.stride_q = 1; a.stride_r = nx; qax = 0; rax = 1; }
+    a.nq = c->n[qax];
+    a.nr = c->n[rax];
+    a.tiles_q = (a.nq + P - 1) / P;
+    a.ntiles = a.tiles_q * a.nr;
+    a.tiles_per_xcd = (a.ntiles + 7) / 8;
+    const T *dummy;
+    tabs(axis, a.dx, a.xc, a.xf, dummy, dummy);
+    const T *t0, *t1, *t2;
+    tabs(qax, t0, t1, t2, a.dx_q, a.xc_q);
+    tabs(rax, t0, t1, t2, a.dx_r, a.xc_r);
+    a.bc_lo = c->bc_lo[axis];
+    a.bc_hi = c->bc_hi[axis];
+    a.gamma = (T)c->gamma;
+    a.dt = (T)dt;
+    a.dt_dev = dt_dev;
+    a.has_bd = has_background(c) ? 1 : 0;
+    a.dip_m = (T)c->dip_m;
+    a.dir_x = (T)c->dir[0]; a.dir_y = (T)c->dir[1]; a.dir_z = (T)c->dir[2];
+    a.bext_x = (T)c->bext[0]; a.bext_y = (T)c->bext[1]; a.bext_z = (T)c->bext[2];
+    a.in_rho = (T)c->inflow[0];
+    a.in_vx = (T)c->inflow[1]; a.in_vy = (T)c->inflow[2]; a.in_vz = (T)c->inflow[3];
+    a.in_bx = (T)c->inflow[4]; a.in_by = (T)c->inflow[5]; a.in_bz = (T)c->inflow[6];
+    a.in_p = (T)c->inflow[7];
+    a.has_inner = c->r_inner > 0.0 ? 1 : 0;
+    a.r_inner2 = (T)(c->r_inner * c->r_inner);
+    a.inner_rho = (T)c->inner_rho;
+    a.inner_E = (T)(c->inner_p / (c->gamma - 1.0));
+    a.flatten = c->opt.flatten;
+    a.janhunen = c->opt.janhunen;
+    a.max_iter = c->opt.max_iter;
+    a.tol = (T)(f64 ? c->opt.tol_f64 : c->opt.tol_f32);
+    a.p_floor = (T)c->opt.p_floor;
+    a.stats = c->opt.collect_stats ? c->d_stats : nullptr;
+    a.cfl_max = c->d_cflmax;
+    a.dxw_x = c->tab[0].dxi64; a.dxw_y = c->tab[1].dxi64; a.dxw_z = c->tab[2].dxi64;
+    a.xcw_x = c->tab[0].xci64; a.xcw_y = c->tab[1].xci64; a.xcw_z = c->tab[2].xci64;
+}
+
+template <int AX, typename T, bool STATS, bool FUSE, int LB>
+ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
+{
+    const int threads = block_threads(a.P, a.M);
+    const size_t lds = (size_t)(kSlotsA + kSlotsB) * a.S * sizeof(T);
+    const int blocks = 8 * a.tiles_per_xcd;
+    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, LB>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute");
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, a);
+    return hip_check(c, hipGetLastError(), "sweep launch");
+}
+
+template <int AX, typename T>
+ppmlr_status launch_axis(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st, bool stats, bool fuse)
+{
+    const bool big = block_threads(a.P, a.M) > 512;
+#define PPMLR_L(S_, F_)                                                         \
+    return big ? launch_one<AX, T, S_, F_, 1024>(c, a, st) : launch_one<AX, T, S_, F_, 512>(c, a, st);
+    if (stats) {
+        if (fuse) { PPMLR_L(true, true) } else { PPMLR_L(true, false) }
+    } else {
+        if (fuse) { PPMLR_L(false, true) } else { PPMLR_L(false, false) }
+    }
+#undef PPMLR_L
+}
+
+template <typename T>
+ppmlr_status sweep_typed(ppmlr_ctx *c, T *u, hipStream_t st, double dt, const double *dt_dev, int axis, bool fuse)
+{
+    const int P = pick_tile(c, axis, (int)sizeof(T));
+    const int M = c->n[axis] + 2 * kG;
+    if (block_threads(P, M) > 1024 || (size_t)(kSlotsA + kSlotsB) * P * M * sizeof(T) > 160 * 1024)
+        return fail(c, PPMLR_EINVAL, "tile does not fit one workgroup");
+    ppmlr::SweepArgs<T> a;
+    fill_args(c, a, u, axis, dt, dt_dev, P);
+    const bool stats = c->opt.collect_stats != 0;
+    if (axis == 0) return launch_axis<0, T>(c, a, st, stats, fuse);
+    if (axis == 1) return launch_axis<1, T>(c, a, st, stats, fuse);
+    return launch_axis<2, T>(c, a, st, stats, fuse);
+}
+
+ppmlr_status check_state(ppmlr_ctx *c, const ppmlr_state *s)
+{
+    if (!c) return PPMLR_EINVAL;
+    if (!s || !s->u) return fail(c, PPMLR_EINVAL, "null state");
+    if (s->dtype != PPMLR_F32 && s->dtype != PPMLR_F64) return fail(c, PPMLR_EINVAL, "bad dtype");
+    return PPMLR_OK;
+}
+
+hipEvent_t pooled_event(ppmlr_ctx *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ppmlr_status do_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, const double *dt_dev, int axis, bool fuse)
+{
+    hipStream_t st = (hipStream_t)s->stream;
+    ppmlr_ctx::Mark mk{nullptr, nullptr, axis};
+    if (c->profiling) {
+        mk.start = pooled_event(c);
+        mk.stop = pooled_event(c);
+        if (!mk.start || !mk.stop) return fail(c, PPMLR_EDEVICE, "hipEventCreate failed");
+        ppmlr_status e = hip_check(c, hipEventRecord(mk.start, st), "hipEventRecord");
+        if (e) return e;
+    }
+    ppmlr_status r = (s->dtype == PPMLR_F64) ? sweep_typed<double>(c, (double *)s->u, st, dt, dt_dev, axis, fuse)
+                                             : sweep_typed<float>(c, (float *)s->u, st, dt, dt_dev, axis, fuse);
+    if (c->profiling) {
+        ppmlr_status e = hip_check(c, hipEventRecord(mk.stop, st), "hipEventRecord");
+        if (e) return e;
+        c->marks.push_back(mk);
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- CFL
+
+template <typename T>
+struct CflArgs {
+    const T *u;
+    int nx, ny, nz;
+    long long vol;
+    const double *dx, *dy, *dz, *xc, *yc, *zc;
+    double gamma, p_floor, r_inner2;
+    int has_inner;
+    double dip_m, dir[3], bext[3];
+    unsigned long long *out;
+};
+
+__device__ inline void bg64(double dip_m, const double *dir, const double *bext, double x, double y, double z,
+                            double &bx, double &by, double &bz)
+{
+    bx = bext[0];
+    by = bext[1];
+    bz = bext[2];
+    if (dip_m != 0.0) {
+        double r2 = x * x + y * y + z * z;
+        double ir = 1.0 / __builtin_sqrt(r2);
+        double ir3 = ir * ir * ir;
+        double ir5 = ir3 * ir * ir;
+        double mr = dir[0] * x + dir[1] * y + dir[2] * z;
+        double cc = 3.0 * mr * ir5;
+        bx += dip_m * (cc * x - dir[0] * ir3);
+        by += dip_m * (cc * y - dir[1] * ir3);
+        bz += dip_m * (cc * z - dir[2] * ir3);
+    }
+}
+
+// Signal-speed maximum over all zones outside the inner boundary: per zone
+// max_a (|v_a| + c_f,a) / dx_a in FP64; wave shuffles, then one atomic per
+// workgroup on the bits of the (non-negative) double.
+template <typename T>
+__global__ void __launch_bounds__(256) cfl_kernel(const CflArgs<T> a)
+{
+    __shared__ double red[4];
+    double smax = 0.0;
+    for (long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x; z < a.vol;
+         z += (long long)gridDim.x * blockDim.x) {
+        int i = (int)(z % a.nx);
+        int j = (int)((z / a.nx) % a.ny);
+        int k = (int)(z / ((long long)a.nx * a.ny));
+        double x = a.xc[i], y = a.yc[j], zz = a.zc[k];
+        if (a.has_inner && x * x + y * y + zz * zz < a.r_inner2) continue;
+        double r = (double)a.u[z];
+        double vx = (double)a.u[a.vol + z] / r, vy = (double)a.u[2 * a.vol + z] / r, vz = (double)a.u[3 * a.vol + z] / r;
+        double px = (double)a.u[4 * a.vol + z], py = (double)a.u[5 * a.vol + z], pz = (double)a.u[6 * a.vol + z];
+        double p = (a.gamma - 1.0) * ((double)a.u[7 * a.vol + z] - 0.5 * r * (vx * vx + vy * vy + vz * vz) -
+                                      0.5 * (px * px + py * py + pz * pz));
+        if (p < a.p_floor) p = a.p_floor;
+        double bx, by, bz;
+        bg64(a.dip_m, a.dir, a.bext, x, y, zz, bx, by, bz);
+        bx += px; by += py; bz += pz;
+        double a2 = a.gamma * p / r;
+        double b2 = (bx * bx + by * by + bz * bz) / r;
+        double w[3] = {a.dx[i], a.dy[j], a.dz[k]};
+        double v[3] = {vx, vy, vz};
+        double B[3] = {bx, by, bz};
+        for (int c = 0; c < 3; ++c) {
+            double ba2 = B[c] * B[c] / r;
+            double disc = (a2 + b2) * (a2 + b2) - 4.0 * a2 * ba2;
+            disc = disc > 0.0 ? disc : 0.0;
+            double cf = __builtin_sqrt(0.5 * (a2 + b2 + __builtin_sqrt(disc)));
+            double s = (__builtin_fabs(v[c]) + cf) / w[c];
+            smax = s > smax ? s : smax;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(smax, off);
+        smax = o > smax ? o : smax;
+    }
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = smax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;
+        atomicMax(a.out, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// dt for the next step from the fused signal-speed maximum; accumulates the
+// simulated time and clears the maximum for the next reduction.
+__global__ void dt_kernel(unsigned long long *smax_bits, double *dt, double *t, double cfl)
+{
+    double smax = __longlong_as_double((long long)*smax_bits);
+    double d = smax > 0.0 ? cfl / smax : 0.0;
+    *dt = d;
+    *t += d;
+    *smax_bits = 0ull;
+}
+
+__global__ void clear_u64(unsigned long long *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+__global__ void clear_f64(double *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------- totals
+
+// Volume integrals in a fixed order: block b sums the contiguous chunk b of
+// the zones (each thread a fixed strided subset, then a fixed tree), then a
+// single block sums the partials in index order.
+template <typename T>
+__global__ void __launch_bounds__(256) totals_partial(const T *u, long long vol, int nx, int ny, const double *dx,
+                                                      const double *dy, const double *dz, double *partials)
+{
+    __shared__ double red[8][256];
+    const long long chunk = (vol + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < vol ? lo + chunk : vol;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long z = lo + threadIdx.x; z < hi; z += blockDim.x) {
+        int i = (int)(z % nx);
+        int j = (int)((z / nx) % ny);
+        int k = (int)(z / ((long long)nx * ny));
+        double dv = dx[i] * dy[j] * dz[k];
+        for (int v = 0; v < 8; ++v) acc[v] += (double)u[v * vol + z] * dv;
+    }
+    for (int v = 0; v < 8; ++v) red[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int v = 0; v < 8; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) partials[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void totals_final(const double *partials, int nblocks, double *out)
+{
+    if (threadIdx.x < 8) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partials[b * 8 + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <typename T>
+ppmlr_status cfl_typed(ppmlr_ctx *c, const T *u, hipStream_t st)
+{
+    CflArgs<T> a;
+    a.u = u;
+    a.nx = c->n[0]; a.ny = c->n[1]; a.nz = c->n[2];
+    a.vol = (long long)a.nx * a.ny * a.nz;
+    a.dx = c->tab[0].dxi64; a.dy = c->tab[1].dxi64; a.dz = c->tab[2].dxi64;
+    a.xc = c->tab[0].xci64; a.yc = c->tab[1].xci64; a.zc = c->tab[2].xci64;
+    a.gamma = c->gamma;
+    a.p_floor = c->opt.p_floor;
+    a.r_inner2 = c->r_inner * c->r_inner;
+    a.has_inner = c->r_inner > 0.0;
+    a.dip_m = c->dip_m;
+    for (int k = 0; k < 3; ++k) { a.dir[k] = c->dir[k]; a.bext[k] = c->bext[k]; }
+    a.out = c->d_cflmax;
+    long long blocks = (a.vol + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(cfl_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hip_check(c, hipGetLastError(), "cfl launch");
+}
+
+ppmlr_status cfl_launch(ppmlr_ctx *c, const ppmlr_state *s)
+{
+    hipStream_t st = (hipStream_t)s->stream;
+    hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, st, c->d_cflmax, 1);
+    if (s->dtype == PPMLR_F64) return cfl_typed<double>(c, (const double *)s->u, st);
+    return cfl_typed<float>(c, (const float *)s->u, st);
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+void ppmlr_default_options(ppmlr_options *o)
+{
+    if (!o) return;
+    o->flatten = 1;
+    o->janhunen = 1;
+    o->max_iter = 20;
+    o->tol_f64 = 1e-12;
+    o->tol_f32 = 1e-6;
+    o->p_floor = 1e-8;
+    o->collect_stats = 1;
+    o->debug_cfl = 0;
+}
+
+ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coords *coords,
+                          const ppmlr_options *opt, ppmlr_ctx **out)
+{
+    if (!out) return PPMLR_EINVAL;
+    *out = nullptr;
+    if (!grid || !coords || !(gamma > 1.0)) return PPMLR_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 1 || !coords->faces[a]) return PPMLR_EINVAL;
+        int lo = grid->bc_lo[a], hi = grid->bc_hi[a];
+        if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return PPMLR_EINVAL;
+        if ((lo == PPMLR_PERIODIC) != (hi == PPMLR_PERIODIC)) return PPMLR_EINVAL;
+        if (lo != PPMLR_PERIODIC && grid->n[a] < kG) return PPMLR_EINVAL;
+        if (grid->n[a] + 2 * kG > 1024) return PPMLR_EINVAL;   // one pencil per workgroup at most
+        for (int i = 0; i < grid->n[a]; ++i)
+            if (!(coords->faces[a][i + 1] > coords->faces[a][i]) || !std::isfinite(coords->faces[a][i + 1]))
+                return PPMLR_EINVAL;
+    }
+    ppmlr_ctx *c = new ppmlr_ctx();
+    for (int a = 0; a < 3; ++a) {
+        c->n[a] = grid->n[a];
+        c->bc_lo[a] = grid->bc_lo[a];
+        c->bc_hi[a] = grid->bc_hi[a];
+        c->faces[a].assign(coords->faces[a], coords->faces[a] + grid->n[a] + 1);
+    }
+    c->r_inner = grid->r_inner;
+    c->gamma = gamma;
+    if (opt) c->opt = *opt;
+    else ppmlr_default_options(&c->opt);
+    if (c->opt.max_iter < 0 || !(c->opt.tol_f64 > 0) || !(c->opt.tol_f32 > 0)) {
+        delete c;
+        return PPMLR_EINVAL;
+    }
+    ppmlr_status s = hip_check(c, hipGetDevice(&c->device), "hipGetDevice");
+    for (int a = 0; a < 3 && !s; ++a) {
+        extend_axis(c, a);
+        AxisTables &t = c->tab[a];
+        std::vector<double> dxi(c->n[a]), xci(c->n[a]);
+        for (int i = 0; i < c->n[a]; ++i) {
+            dxi[i] = c->faces[a][i + 1] - c->faces[a][i];
+            xci[i] = 0.5 * (c->faces[a][i] + c->faces[a][i + 1]);
+        }
+        if (!s) s = upload(c, &t.dx64, c->ext_dx[a]);
+        if (!s) s = upload(c, &t.xc64, c->ext_xc[a]);
+        if (!s) s = upload(c, &t.xf64, c->ext_xf[a]);
+        if (!s) s = upload(c, &t.dxi64, dxi);
+        if (!s) s = upload(c, &t.xci64, xci);
+        if (!s) s = upload(c, &t.dx32, c->ext_dx[a]);
+        if (!s) s = upload(c, &t.xc32, c->ext_xc[a]);
+        if (!s) s = upload(c, &t.xf32, c->ext_xf[a]);
+        if (!s) s = upload(c, &t.dxi32, dxi);
+        if (!s) s = upload(c, &t.xci32, xci);
+    }
+    c->partial_blocks = kTotBlocks;
+    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_stats, sizeof(unsigned long long) * kStatWords), "hipMalloc");
+    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_cflmax, sizeof(unsigned long long)), "hipMalloc");
+    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_dt, sizeof(double)), "hipMalloc");
+    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_time, sizeof(double)), "hipMalloc");
+    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_partials, sizeof(double) * (8 * kTotBlocks + 8)), "hipMalloc");
+    if (!s) {
+        hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_stats, kStatWords);
+        hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_cflmax, 1);
+        hipLaunchKernelGGL(clear_f64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_dt, 1);
+        hipLaunchKernelGGL(clear_f64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_time, 1);
+        s = hip_check(c, hipDeviceSynchronize(), "init");
+    }
+    if (s) {
+        free_tables(c);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return PPMLR_OK;
+}
+
+void ppmlr_destroy(ppmlr_ctx *c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (auto &m : c->marks) {
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    free_tables(c);
+    delete c;
+}
+
+ppmlr_status ppmlr_set_profiling(ppmlr_ctx *c, int enable)
+{
+    if (!c) return PPMLR_EINVAL;
+    c->profiling = enable != 0;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_kernel_times(ppmlr_ctx *c, double ms[3], long long launches[3])
+{
+    if (!c || !ms || !launches) return PPMLR_EINVAL;
+    for (int a = 0; a < 3; ++a) { ms[a] = 0.0; launches[a] = 0; }
+    ppmlr_status e = PPMLR_OK;
+    for (auto &m : c->marks) {
+        if (!e) e = hip_check(c, hipEventSynchronize(m.stop), "hipEventSynchronize");
+        float t = 0.0f;
+        if (!e) e = hip_check(c, hipEventElapsedTime(&t, m.start, m.stop), "hipEventElapsedTime");
+        if (!e) { ms[m.axis] += (double)t; launches[m.axis] += 1; }
+        c->event_pool.push_back(m.start);
+        c->event_pool.push_back(m.stop);
+    }
+    c->marks.clear();
+    return e;
+}
+
+const char *ppmlr_last_error(const ppmlr_ctx *c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+ppmlr_status ppmlr_set_dipole(ppmlr_ctx *c, double moment, const double dir[3])
+{
+    if (!c) return PPMLR_EINVAL;
+    if (!std::isfinite(moment)) return fail(c, PPMLR_EINVAL, "bad moment");
+    if (moment != 0.0) {
+        if (!dir) return fail(c, PPMLR_EINVAL, "null direction");
+        double n2 = dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2];
+        if (!(n2 > 0.0) || !std::isfinite(n2)) return fail(c, PPMLR_EINVAL, "bad direction");
+        for (int k = 0; k < 3; ++k) c->dir[k] = dir[k] / std::sqrt(n2);
+    }
+    c->dip_m = moment;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_background(ppmlr_ctx *c, const double b[3])
+{
+    if (!c || !b) return PPMLR_EINVAL;
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(b[k])) return fail(c, PPMLR_EINVAL, "bad field");
+        c->bext[k] = b[k];
+    }
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_inflow(ppmlr_ctx *c, const double prim[8])
+{
+    if (!c || !prim) return PPMLR_EINVAL;
+    for (int k = 0; k < 8; ++k)
+        if (!std::isfinite(prim[k])) return fail(c, PPMLR_EINVAL, "non-finite inflow");
+    if (!(prim[0] > 0.0) || !(prim[7] > 0.0)) return fail(c, PPMLR_EINVAL, "inflow needs rho > 0, p > 0");
+    std::memcpy(c->inflow, prim, sizeof(double) * 8);
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_inner(ppmlr_ctx *c, double rho, double p)
+{
+    if (!c) return PPMLR_EINVAL;
+    if (!(rho > 0.0) || !(p > 0.0) || !std::isfinite(rho) || !std::isfinite(p))
+        return fail(c, PPMLR_EINVAL, "inner state needs rho > 0, p > 0");
+    c->inner_rho = rho;
+    c->inner_p = p;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, int axis)
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (axis < 0 || axis > 2) return fail(c, PPMLR_EINVAL, "axis must be 0, 1 or 2");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, PPMLR_EINVAL, "dt must be positive and finite");
+    return do_sweep(c, s, dt, nullptr, axis, false);
+}
+
+ppmlr_status ppmlr_step(ppmlr_ctx *c, const ppmlr_state *s, double dt)
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, PPMLR_EINVAL, "dt must be positive and finite");
+    if (c->opt.debug_cfl) {
+        double lim = 0.0;
+        e = ppmlr_cfl_dt(c, s, 1.0, &lim);
+        if (e) return e;
+        if (dt > 1.0001 * lim) return fail(c, PPMLR_ECFL, "dt above the CFL limit");
+    }
+    static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    const int *ord = (c->step % 2 == 0) ? even : odd;
+    for (int k = 0; k < 3; ++k) {
+        e = do_sweep(c, s, dt, nullptr, ord[k], false);
+        if (e) return e;
+    }
+    c->step++;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_step_index(ppmlr_ctx *c, long long step)
+{
+    if (!c || step < 0) return PPMLR_EINVAL;
+    c->step = step;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_get_step_index(const ppmlr_ctx *c, long long *step)
+{
+    if (!c || !step) return PPMLR_EINVAL;
+    *step = c->step;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_cfl_dt(ppmlr_ctx *c, const ppmlr_state *s, double cfl, double *dt_out)
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (!dt_out || !(cfl > 0.0)) return fail(c, PPMLR_EINVAL, "cfl must be positive");
+    e = cfl_launch(c, s);
+    if (e) return e;
+    unsigned long long bits = 0;
+    hipStream_t st = (hipStream_t)s->stream;
+    e = hip_check(c, hipMemcpyAsync(&bits, c->d_cflmax, sizeof(bits), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (e) return e;
+    double smax;
+    std::memcpy(&smax, &bits, sizeof(smax));
+    if (!(smax > 0.0) || !std::isfinite(smax)) return fail(c, PPMLR_ENONPHYS, "no finite signal speed");
+    *dt_out = cfl / smax;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_advance(ppmlr_ctx *c, const ppmlr_state *s, int nsteps, double cfl)
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (nsteps < 0 || !(cfl > 0.0)) return fail(c, PPMLR_EINVAL, "nsteps >= 0 and cfl > 0 required");
+    if (nsteps == 0) return PPMLR_OK;
+    hipStream_t st = (hipStream_t)s->stream;
+    e = cfl_launch(c, s);   // signal-speed maximum of the current state
+    if (e) return e;
+    static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    for (int n = 0; n < nsteps; ++n) {
+        hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(1), 0, st, c->d_cflmax, c->d_dt, c->d_time, cfl);
+        const int *ord = (c->step % 2 == 0) ? even : odd;
+        for (int k = 0; k < 3; ++k) {
+            e = do_sweep(c, s, 0.0, c->d_dt, ord[k], k == 2);
+            if (e) return e;
+        }
+        c->step++;
+    }
+    return hip_check(c, hipGetLastError(), "advance");
+}
+
+ppmlr_status ppmlr_time(ppmlr_ctx *c, const ppmlr_state *s, double *t_out)
+{
+    if (!c || !t_out) return PPMLR_EINVAL;
+    hipStream_t st = s ? (hipStream_t)s->stream : (hipStream_t)0;
+    ppmlr_status e = hip_check(c, hipMemcpyAsync(t_out, c->d_time, sizeof(double), hipMemcpyDeviceToHost, st),
+                               "hipMemcpyAsync");
+    if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    return e;
+}
+
+ppmlr_status ppmlr_totals(ppmlr_ctx *c, const ppmlr_state *s, double out[8])
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (!out) return fail(c, PPMLR_EINVAL, "null output");
+    hipStream_t st = (hipStream_t)s->stream;
+    const long long vol = (long long)c->n[0] * c->n[1] * c->n[2];
+    if (s->dtype == PPMLR_F64)
+        hipLaunchKernelGGL(totals_partial<double>, dim3(kTotBlocks), dim3(256), 0, st, (const double *)s->u, vol,
+                           c->n[0], c->n[1], c->tab[0].dxi64, c->tab[1].dxi64, c->tab[2].dxi64, c->d_partials);
+    else
+        hipLaunchKernelGGL(totals_partial<float>, dim3(kTotBlocks), dim3(256), 0, st, (const float *)s->u, vol,
+                           c->n[0], c->n[1], c->tab[0].dxi64, c->tab[1].dxi64, c->tab[2].dxi64, c->d_partials);
+    hipLaunchKernelGGL(totals_final, dim3(1), dim3(64), 0, st, c->d_partials, kTotBlocks, c->d_partials + 8 * kTotBlocks);
+    e = hip_check(c, hipGetLastError(), "totals launch");
+    if (!e) e = hip_check(c, hipMemcpyAsync(out, c->d_partials + 8 * kTotBlocks, sizeof(double) * 8,
+                                            hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    return e;
+}
+
+ppmlr_status ppmlr_stats(ppmlr_ctx *c, void *stream, ppmlr_stats_t *out)
+{
+    if (!c || !out) return PPMLR_EINVAL;
+    unsigned long long h[kStatWords];
+    hipStream_t st = (hipStream_t)stream;
+    ppmlr_status e = hip_check(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (e) return e;
+    for (int b = 0; b < 32; ++b) out->iters_hist[b] = (long long)h[b];
+    out->floor_hits = (long long)h[32];
+    out->nonconverged = (long long)h[33];
+    out->nonphys = (long long)h[34];
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_reset_stats(ppmlr_ctx *c, void *stream)
+{
+    if (!c) return PPMLR_EINVAL;
+    hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_stats, kStatWords);
+    return hip_check(c, hipGetLastError(), "reset stats");
+}
+
+ppmlr_status ppmlr_status_check(ppmlr_ctx *c, void *stream)
+{
+    ppmlr_stats_t s;
+    ppmlr_status e = ppmlr_stats(c, stream, &s);
+    if (e) return e;
+    if (s.nonphys > 0) return fail(c, PPMLR_ENONPHYS, "non-physical zones entered a sweep");
+    if (s.nonconverged > 0) return fail(c, PPMLR_ERIEMANN, "Riemann iteration limit reached");
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_tile(ppmlr_ctx *c, int axis, int pencils)
+{
+    if (!c || axis < 0 || axis > 2 || pencils < 0) return PPMLR_EINVAL;
+    if (pencils > 0) {
+        int M = c->n[axis] + 2 * kG;
+        if (block_threads(pencils, M) > 1024) return fail(c, PPMLR_EINVAL, "tile exceeds 1024 threads");
+        if ((size_t)(kSlotsA + kSlotsB) * pencils * M * 4 > 160 * 1024)
+            return fail(c, PPMLR_EINVAL, "tile exceeds the LDS budget");
+    }
+    c->tile[axis] = pencils;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_get_tile(const ppmlr_ctx *c, int axis, int dtype, int *pencils)
+{
+    if (!c || axis < 0 || axis > 2 || !pencils) return PPMLR_EINVAL;
+    *pencils = pick_tile(c, axis, dtype == PPMLR_F64 ? 8 : 4);
+    return PPMLR_OK;
+}
+
+}  // extern "C"

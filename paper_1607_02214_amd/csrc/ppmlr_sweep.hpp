@@ -1,0 +1,727 @@
+// ppmlr_sweep.hpp -- gfx950 device code of one dimensionally split PPMLR-MHD
+// sweep (paper, Section II: zone-centred averages, parabolic distribution in
+// each zone, characteristic edge values, Lagrangian update with an interface
+// Riemann solve, remap onto the Eulerian grid; Section III-A: one independent
+// 1D problem per pencil).
+//
+// Execution model: one thread per zone, a workgroup owns P whole pencils
+// (N interior zones + 7 ghosts per side each), so the update is done in place
+// and every stencil is served from LDS.  Successive stages exchange only what
+// a neighbour needs, through two LDS buffers used alternately (A, B) with one
+// barrier per exchange:
+//   R1 load + primitives                         -> A
+//   R2 edge values (mass coordinate), shock test  A -> B
+//   R3 parabolas, tracing, interface states       B -> A
+//   R4 Riemann solves, Lagrangian fluxes          A -> B
+//   R5 Lagrangian zone contents                   B -> A
+//   R6 remap edge values (volume coordinate)      A -> B
+//   R7 remap parabolas, donor-cell fluxes         B -> A
+//   R8 conservative update, sources, store        A
+// The pencil axis is a template parameter so that all component indexing is
+// static (no private arrays with dynamic indices).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppmlr {
+
+constexpr int kG = 7;           // ghost zones per side
+constexpr int kSlotsA = 14;     // values per zone in LDS buffer A
+constexpr int kSlotsB = 8;      // values per zone in LDS buffer B
+constexpr int kStatWords = 35;  // iteration histogram [32], floors, nonconverged, nonphys
+
+enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
+
+// Arithmetic helpers: FP64 uses IEEE division and square root, FP32 the
+// hardware reciprocal / square-root approximations (1 ulp).
+template <typename T> struct Ar;
+template <> struct Ar<double> {
+    __device__ static inline double rcp(double x) { return 1.0 / x; }
+    __device__ static inline double div(double a, double b) { return a / b; }
+    __device__ static inline double sqrt_(double x) { return __builtin_sqrt(x); }
+    __device__ static inline double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+};
+template <> struct Ar<float> {
+    __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static inline float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    __device__ static inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    __device__ static inline float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+};
+
+template <typename T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ inline T tabs(T a) { return a < T(0) ? -a : a; }
+template <typename T> __device__ inline T tsgn(T a) { return a > T(0) ? T(1) : (a < T(0) ? T(-1) : T(0)); }
+
+template <typename T>
+struct SweepArgs {
+    T *u;                       // state, SoA [8][nz][ny][nx]
+    long long vol;              // zones per variable
+    int N, M;                   // zones along the pencil, N + 2G
+    int P;                      // pencils per workgroup
+    int S;                      // LDS slots = P * M
+    long long stride_n, stride_q, stride_r;   // element strides
+    int nq, nr;                 // pencils along q (memory-fastest transverse) and r
+    int tiles_q, ntiles, tiles_per_xcd;
+    const T *dx, *xc, *xf;      // sweep axis: extended widths [M], centres [M], faces [M+1]
+    const T *xc_q, *xc_r;       // transverse centres (interior zones)
+    const T *dx_q, *dx_r;       // transverse widths (interior zones)
+    int bc_lo, bc_hi;
+    T gamma;
+    T dt;                       // used when dt_dev == nullptr
+    const double *dt_dev;       // device-resident dt (advance loop)
+    int has_bd;                 // background field present
+    T dip_m, dir_x, dir_y, dir_z, bext_x, bext_y, bext_z;
+    T in_rho, in_vx, in_vy, in_vz, in_bx, in_by, in_bz, in_p;   // inflow (total B)
+    T r_inner2, inner_rho, inner_E;
+    int has_inner;
+    int flatten, janhunen, max_iter;
+    T tol, p_floor;
+    unsigned long long *stats;  // kStatWords counters or nullptr
+    unsigned long long *cfl_max;// fused signal-speed max (double bits) or nullptr
+    const double *dxw_x, *dxw_y, *dxw_z;  // FP64 interior widths of all axes (fused CFL)
+    const double *xcw_x, *xcw_y, *xcw_z;  // FP64 interior centres of all axes (fused CFL)
+};
+
+// Background field B_d = M [3 (m.r) r / r^5 - m / r^3] + b_ext at (x, y, z).
+template <typename T>
+__device__ inline void background(const SweepArgs<T> &a, T x, T y, T z, T &bx, T &by, T &bz)
+{
+    bx = a.bext_x;
+    by = a.bext_y;
+    bz = a.bext_z;
+    if (a.dip_m != T(0)) {
+        T r2 = x * x + y * y + z * z;
+        T ir = Ar<T>::rsqrt(r2);
+        T ir2 = ir * ir;
+        T ir3 = ir2 * ir;
+        T ir5 = ir3 * ir2;
+        T mr = a.dir_x * x + a.dir_y * y + a.dir_z * z;
+        T c = T(3) * mr * ir5;
+        bx += a.dip_m * (c * x - a.dir_x * ir3);
+        by += a.dip_m * (c * y - a.dir_y * ir3);
+        bz += a.dip_m * (c * z - a.dir_z * ir3);
+    }
+}
+
+// Map pencil-frame coordinates (n, t1, t2) of axis AX to (x, y, z) and the
+// field back; t1, t2 are the cyclic successors of the sweep axis.
+template <int AX, typename T>
+__device__ inline void to_xyz(T n, T t1, T t2, T &x, T &y, T &z)
+{
+    if (AX == 0) { x = n; y = t1; z = t2; }
+    else if (AX == 1) { y = n; z = t1; x = t2; }
+    else { z = n; x = t1; y = t2; }
+}
+template <int AX, typename T>
+__device__ inline void to_pencil(T bx, T by, T bz, T &bn, T &b1, T &b2)
+{
+    if (AX == 0) { bn = bx; b1 = by; b2 = bz; }
+    else if (AX == 1) { bn = by; b1 = bz; b2 = bx; }
+    else { bn = bz; b1 = bx; b2 = by; }
+}
+template <int AX, typename T>
+__device__ inline void field_at(const SweepArgs<T> &a, T n, T c1, T c2, T &bn, T &b1, T &b2)
+{
+    T x, y, z, bx, by, bz;
+    to_xyz<AX>(n, c1, c2, x, y, z);
+    background(a, x, y, z, bx, by, bz);
+    to_pencil<AX>(bx, by, bz, bn, b1, b2);
+}
+
+// Edge value a_{j+1/2} on nonuniform widths w0..w3 = w_{j-1..j+2}
+// (Colella & Woodward 1984, Eq. 1.6) from the (limited) slopes of zones j
+// and j+1; the width weights are shared by all variables of a face.
+template <typename T>
+struct EdgeW {
+    T e0, t1, t2, t3, inv4;
+    __device__ inline void init(T w0, T w1, T w2, T w3)
+    {
+        T s12 = w1 + w2;
+        T i12 = Ar<T>::rcp(s12);
+        T d1 = T(2) * w1 + w2;
+        T d2 = w1 + T(2) * w2;
+        T id1 = Ar<T>::rcp(d1);
+        T id2 = Ar<T>::rcp(d2);
+        e0 = w1 * i12;
+        t1 = T(2) * w2 * w1 * i12 * ((w0 + w1) * id1 - (w3 + w2) * id2);
+        t2 = -w1 * (w0 + w1) * id1;
+        t3 = w2 * (w2 + w3) * id2;
+        inv4 = Ar<T>::rcp(w0 + w1 + w2 + w3);
+    }
+    __device__ inline T edge(T aj, T ajp, T daj, T dajp) const
+    {
+        T d = ajp - aj;
+        return aj + e0 * d + (t1 * d + t2 * dajp + t3 * daj) * inv4;
+    }
+};
+
+// Average slope times width in zone j on widths wm, w0, wp (CW84 Eq. 1.7),
+// then limited (Eq. 1.8).
+template <typename T>
+struct SlopeW {
+    T cs, cp, cm;
+    __device__ inline void init(T wm, T w0, T wp)
+    {
+        cs = w0 * Ar<T>::rcp(wm + w0 + wp);
+        cp = (T(2) * wm + w0) * Ar<T>::rcp(wp + w0);
+        cm = (w0 + T(2) * wp) * Ar<T>::rcp(wm + w0);
+    }
+    __device__ inline T slope(T am, T a0, T ap) const
+    {
+        T dp = ap - a0;
+        T dm = a0 - am;
+        T da = cs * (cp * dp + cm * dm);
+        if (dp * dm > T(0)) {
+            T m = tmin(tabs(da), tmin(T(2) * tabs(dm), T(2) * tabs(dp)));
+            return da < T(0) ? -m : (da > T(0) ? m : T(0));
+        }
+        return T(0);
+    }
+};
+
+// Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity.
+template <typename T>
+__device__ inline void parabola(T a, T aL, T aR, T f, T &oL, T &oD, T &o6)
+{
+    aL = aL + f * (a - aL);
+    aR = aR + f * (a - aR);
+    if ((aR - a) * (a - aL) <= T(0)) {
+        aL = a;
+        aR = a;
+    } else {
+        T dA = aR - aL;
+        T a6 = T(6) * (a - T(0.5) * (aL + aR));
+        if (dA * a6 > dA * dA) aL = T(3) * a - T(2) * aR;
+        else if (-dA * dA > dA * a6) aR = T(3) * a - T(2) * aL;
+    }
+    oL = aL;
+    oD = aR - aL;
+    o6 = T(6) * (a - T(0.5) * (aL + aR));
+}
+
+// Averages of a zone parabola over the fraction y next to its right edge
+// (avgR) or left edge (avgL) (CW84 Eq. 1.12).
+template <typename T>
+__device__ inline T avgR(T aL, T dA, T a6, T y)
+{
+    return (aL + dA) - T(0.5) * y * (dA - (T(1) - (T(2) / T(3)) * y) * a6);
+}
+template <typename T>
+__device__ inline T avgL(T aL, T dA, T a6, T y)
+{
+    return aL + T(0.5) * y * (dA + (T(1) - (T(2) / T(3)) * y) * a6);
+}
+
+// Wave-level counter update: one atomic per wave and non-empty bin.
+__device__ inline void wave_count(unsigned long long *ctr, bool pred)
+{
+    unsigned long long m = __ballot(pred);
+    if (m != 0ull) {
+        int lane = __lane_id();
+        unsigned long long lower = m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+        if (pred && lower == 0ull) atomicAdd(ctr, (unsigned long long)__popcll(m));
+    }
+}
+
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int LB>
+__global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sA = reinterpret_cast<T *>(smem_raw);
+    T *sB = sA + kSlotsA * a.S;
+    __shared__ double s_red[16];
+
+    // XCD-aware tile order: consecutive workgroups go to different XCDs
+    // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
+    // tiles and share L2 lines of neighbouring pencils.
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+    if (tile >= a.ntiles) return;
+    const int tq = tile % a.tiles_q;
+    const int r = tile / a.tiles_q;
+    const int q0 = tq * a.P;
+
+    const int tid = threadIdx.x;
+    const int S = a.S, M = a.M, N = a.N, P = a.P;
+    const bool slot_ok = tid < S;
+    int p, i;
+    if (AX == 0) { p = tid / M; i = tid - p * M; }       // zones of a pencil adjacent
+    else { i = tid / P; p = tid - i * P; }                // pencils adjacent (coalesced)
+    const int d = (AX == 0) ? 1 : P;                      // slot offset of zone i+1
+    const int q = q0 + p;
+    const bool pen = slot_ok && q < a.nq;
+    const int g = i - kG;                                 // zone index along the pencil
+    const bool interior = pen && g >= 0 && g < N;
+    const int tsafe = slot_ok ? tid : S - 1;              // padding lanes read a valid slot
+    auto nb = [&](int k) -> int {                         // slot of zone i+k (clamped)
+        int ii = i + k;
+        return (ii >= 0 && ii < M && slot_ok) ? tid + k * d : tsafe;
+    };
+    const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
+    const T gam = a.gamma;
+
+    // transverse coordinates of the pencil
+    const int qq = q < a.nq ? q : a.nq - 1;
+    int j1, j2;
+    T c1, c2;
+    // q is t1 for the x and z sweeps, t2 for the y sweep
+    if (AX == 1) { j1 = r; j2 = qq; c1 = a.xc_r[r]; c2 = a.xc_q[qq]; }
+    else { j1 = qq; j2 = r; c1 = a.xc_q[qq]; c2 = a.xc_r[r]; }
+    (void)j1; (void)j2;
+    const long long base = (long long)qq * a.stride_q + (long long)r * a.stride_r;
+
+    // ------------------------------------------------------------ R1
+    const int ic = i < M ? i : M - 1;
+    const T dxi = a.dx[ic];
+    const T xci = a.xc[ic];
+    const T xfr = a.xf[ic + 1];
+    int src = g;
+    bool inflow_zone = false;
+    if (g < 0) {
+        if (a.bc_lo == kPeriodic) { src = g % N; if (src < 0) src += N; }
+        else if (a.bc_lo == kOutflow) src = 0;
+        else inflow_zone = true;
+    } else if (g >= N) {
+        if (a.bc_hi == kPeriodic) src = g % N;
+        else if (a.bc_hi == kOutflow) src = N - 1;
+        else inflow_zone = true;
+    }
+    // centre and right-face background field (pencil frame)
+    T bdn = 0, bd1 = 0, bd2 = 0, bfn = 0, bf1 = 0, bf2 = 0;
+    if (a.has_bd) {
+        field_at<AX>(a, xci, c1, c2, bdn, bd1, bd2);
+        field_at<AX>(a, xfr, c1, c2, bfn, bf1, bf2);
+    }
+    // conserved state in pencil frame: rho, mn, m1, m2, bn, b1, b2, E
+    T Q[8];
+    constexpr int kn = AX, k1 = (AX + 1) % 3, k2 = (AX + 2) % 3;
+    if (pen && !inflow_zone) {
+        const T *u = a.u + base + (long long)src * a.stride_n;
+        Q[0] = u[0];
+        Q[1] = u[(1 + kn) * a.vol];
+        Q[2] = u[(1 + k1) * a.vol];
+        Q[3] = u[(1 + k2) * a.vol];
+        Q[4] = u[(4 + kn) * a.vol];
+        Q[5] = u[(4 + k1) * a.vol];
+        Q[6] = u[(4 + k2) * a.vol];
+        Q[7] = u[7 * a.vol];
+    } else if (pen) {
+        // inflow ghost: primitive inflow state with B' = B_in - B_d(centre)
+        T vn, v1, v2, Bn, B1, B2;
+        to_pencil<AX>(a.in_vx, a.in_vy, a.in_vz, vn, v1, v2);
+        to_pencil<AX>(a.in_bx, a.in_by, a.in_bz, Bn, B1, B2);
+        T pbn = Bn - bdn, pb1 = B1 - bd1, pb2 = B2 - bd2;
+        Q[0] = a.in_rho;
+        Q[1] = a.in_rho * vn;
+        Q[2] = a.in_rho * v1;
+        Q[3] = a.in_rho * v2;
+        Q[4] = pbn;
+        Q[5] = pb1;
+        Q[6] = pb2;
+        Q[7] = a.in_p / (gam - T(1)) + T(0.5) * a.in_rho * (vn * vn + v1 * v1 + v2 * v2) +
+               T(0.5) * (pbn * pbn + pb1 * pb1 + pb2 * pb2);
+    } else {
+        Q[0] = T(1); Q[1] = Q[2] = Q[3] = T(0); Q[4] = Q[5] = Q[6] = T(0); Q[7] = T(1);
+    }
+    const T rho = Q[0];
+    const T irho = Ar<T>::rcp(rho);
+    const T un = Q[1] * irho, v1 = Q[2] * irho, v2 = Q[3] * irho;
+    const T bn = Q[4], b1 = Q[5], b2 = Q[6];
+    T pth = (gam - T(1)) * (Q[7] - T(0.5) * rho * (un * un + v1 * v1 + v2 * v2) -
+                            T(0.5) * (bn * bn + b1 * b1 + b2 * b2));
+    const bool floored = pth < a.p_floor;
+    if (floored) pth = a.p_floor;
+    const T dm = rho * dxi;
+    const T Pt = pth + bd1 * b1 + bd2 * b2 + T(0.5) * (b1 * b1 + b2 * b2);
+    const T Pa = Pt + T(0.5) * (bd1 * bd1 + bd2 * bd2);
+    if (STATS && a.stats) {
+        bool bad = interior && (!(rho > T(0)) || !__builtin_isfinite(rho) || !__builtin_isfinite(Q[7]));
+        wave_count(&a.stats[32], interior && floored);
+        wave_count(&a.stats[34], bad);
+    }
+    // primitive set used for reconstruction: rho, u, v1, v2, b1, b2, p
+    const T W[7] = {rho, un, v1, v2, b1, b2, pth};
+    if (slot_ok) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) sA[k * S + tid] = W[k];
+        sA[7 * S + tid] = dm;
+        sA[8 * S + tid] = bn;
+        sA[9 * S + tid] = Pt;
+        sA[10 * S + tid] = Pa;
+        sA[11 * S + tid] = bfn;
+        sA[12 * S + tid] = bf1;
+        sA[13 * S + tid] = bf2;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R2
+    const int sm1 = nb(-1), sp1 = nb(1), sp2 = nb(2), sm2 = nb(-2);
+    const T dmm = sA[7 * S + sm1], dmp = sA[7 * S + sp1], dmp2 = sA[7 * S + sp2];
+    const T bnm = sA[8 * S + sm1], bnp = sA[8 * S + sp1];
+    const T bln = sA[11 * S + sm1], bl1 = sA[12 * S + sm1], bl2 = sA[13 * S + sm1];  // left face
+    const T Ptm = sA[9 * S + sm1], Ptp = sA[9 * S + sp1];
+    T edgeR[7];
+    {
+        SlopeW<T> s0, s1;
+        s0.init(dmm, dm, dmp);
+        s1.init(dm, dmp, dmp2);
+        EdgeW<T> ew;
+        ew.init(dmm, dm, dmp, dmp2);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            T am = sA[k * S + sm1], ap = sA[k * S + sp1], ap2 = sA[k * S + sp2];
+            T da0 = s0.slope(am, W[k], ap);
+            T da1 = s1.slope(W[k], ap, ap2);
+            edgeR[k] = ew.edge(W[k], ap, da0, da1);
+        }
+    }
+    T ftil = T(0);
+    if (a.flatten) {
+        T Ptm2 = sA[9 * S + sm2], Ptp2 = sA[9 * S + sp2];
+        T Pam = sA[10 * S + sm1], Pap = sA[10 * S + sp1];
+        T um = sA[1 * S + sm1], up = sA[1 * S + sp1];
+        T d1 = Ptp - Ptm, d2 = Ptp2 - Ptm2;
+        if (tabs(d1) > T(0.33) * tmin(Pap, Pam) && um > up) {
+            if (d2 != T(0)) ftil = tmax(T(0), tmin(T(1), T(10) * (Ar<T>::div(d1, d2) - T(0.75))));
+            else ftil = T(1);
+        }
+    }
+    if (slot_ok) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) sB[k * S + tid] = edgeR[k];
+        sB[7 * S + tid] = ftil;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R3
+    T fl = T(0);
+    if (a.flatten) {
+        T fm = sB[7 * S + sm1], fp = sB[7 * S + sp1];
+        fl = tmax(ftil, (Ptp - Ptm < T(0)) ? fp : fm);
+    }
+    T pLc[7], pDc[7], p6c[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        T aL = sB[k * S + sm1];
+        parabola(W[k], aL, edgeR[k], fl, pLc[k], pDc[k], p6c[k]);
+    }
+    // tracing speeds (Lagrangian): normal pair C_n, Alfven pair C_A
+    const T Bt1c = bd1 + b1, Bt2c = bd2 + b2, Bnc = bdn + bn;
+    const T Cn = Ar<T>::sqrt_(rho * (gam * pth + Bt1c * Bt1c + Bt2c * Bt2c));
+    const T CA = Ar<T>::sqrt_(rho) * tabs(Bnc);
+    const T idm = Ar<T>::rcp(dm);
+    const T yn = tmin(T(1), Cn * dt * idm);
+    const T yA = tmin(T(1), CA * dt * idm);
+    // time-centring of the couplings left out of the two decoupled Riemann
+    // problems: oblique-field terms and the variation of B_n along the pencil
+    const T hdt = T(0.5) * dt;
+    const T dbn = (bnp - bnm) * Ar<T>::rcp(T(0.5) * dmm + dm + T(0.5) * dmp);
+    const T ddn = (bfn - bln) * idm, dd1 = (bf1 - bl1) * idm, dd2 = (bf2 - bl2) * idm;
+    const T dBn = ddn + dbn;
+    T corrP = hdt * rho * Bnc * (Bt1c * pDc[2] + Bt2c * pDc[3]) * idm;
+    T corrB1 = -hdt * rho * Bt1c * pDc[1] * idm;
+    T corrB2 = -hdt * rho * Bt2c * pDc[1] * idm;
+    const T corrU = hdt * (Bnc * dbn + bn * ddn);
+    const T corrV1 = hdt * (b1 * dBn + bd1 * dbn + bn * dd1);
+    const T corrV2 = hdt * (b2 * dBn + bd2 * dbn + bn * dd2);
+    corrB1 += hdt * rho * (v1 * dBn - un * dd1);
+    corrB2 += hdt * rho * (v2 * dBn - un * dd2);
+    corrP += hdt * rho * ((Bt1c * v1 + Bt2c * v2) * dBn - un * (Bt1c * dd1 + Bt2c * dd2));
+
+    // interface states of this zone: L at its right face (i+1/2), R at its
+    // left face (i-1/2); normal pair traced with y_n, Alfven pair with y_A
+    // right-face (L) state, kept in registers
+    T LPt, Lu, LC, Lk, Lr, Lv1, Lv2, Lb1, Lb2;
+    {
+        T r_ = avgR(pLc[0], pDc[0], p6c[0], yn);
+        T u_ = avgR(pLc[1], pDc[1], p6c[1], yn);
+        T p_ = avgR(pLc[6], pDc[6], p6c[6], yn);
+        T c1_ = avgR(pLc[4], pDc[4], p6c[4], yn);
+        T c2_ = avgR(pLc[5], pDc[5], p6c[5], yn);
+        T T1 = bf1 + c1_, T2 = bf2 + c2_;
+        T C = Ar<T>::sqrt_(r_ * (gam * p_ + T1 * T1 + T2 * T2));
+        T P0 = p_ + T(0.5) * (T1 * T1 + T2 * T2);
+        T Pd = T(0.5) * (bf1 * bf1 + bf2 * bf2);
+        T Pt_ = p_ + bf1 * c1_ + bf2 * c2_ + T(0.5) * (c1_ * c1_ + c2_ * c2_) + corrP;
+        if (Pt_ + Pd < T(0.5) * P0) Pt_ = T(0.5) * P0 - Pd;
+        T ge = C * C * Ar<T>::rcp(r_ * (Pt_ + Pd));
+        LPt = Pt_;
+        Lu = u_ + corrU;
+        LC = C;
+        Lk = (ge + T(1)) * Ar<T>::rcp(T(2) * ge);
+        Lr = Ar<T>::sqrt_(avgR(pLc[0], pDc[0], p6c[0], yA));
+        Lv1 = avgR(pLc[2], pDc[2], p6c[2], yA) + corrV1;
+        Lv2 = avgR(pLc[3], pDc[3], p6c[3], yA) + corrV2;
+        Lb1 = avgR(pLc[4], pDc[4], p6c[4], yA) + corrB1;
+        Lb2 = avgR(pLc[5], pDc[5], p6c[5], yA) + corrB2;
+    }
+    // left-face (R) state, handed to the zone on the left through LDS
+    {
+        T r_ = avgL(pLc[0], pDc[0], p6c[0], yn);
+        T u_ = avgL(pLc[1], pDc[1], p6c[1], yn);
+        T p_ = avgL(pLc[6], pDc[6], p6c[6], yn);
+        T c1_ = avgL(pLc[4], pDc[4], p6c[4], yn);
+        T c2_ = avgL(pLc[5], pDc[5], p6c[5], yn);
+        T T1 = bl1 + c1_, T2 = bl2 + c2_;
+        T C = Ar<T>::sqrt_(r_ * (gam * p_ + T1 * T1 + T2 * T2));
+        T P0 = p_ + T(0.5) * (T1 * T1 + T2 * T2);
+        T Pd = T(0.5) * (bl1 * bl1 + bl2 * bl2);
+        T Pt_ = p_ + bl1 * c1_ + bl2 * c2_ + T(0.5) * (c1_ * c1_ + c2_ * c2_) + corrP;
+        if (Pt_ + Pd < T(0.5) * P0) Pt_ = T(0.5) * P0 - Pd;
+        T ge = C * C * Ar<T>::rcp(r_ * (Pt_ + Pd));
+        if (slot_ok) {
+            sA[0 * S + tid] = Pt_;
+            sA[1 * S + tid] = u_ + corrU;
+            sA[2 * S + tid] = C;
+            sA[3 * S + tid] = (ge + T(1)) * Ar<T>::rcp(T(2) * ge);
+            sA[4 * S + tid] = Ar<T>::sqrt_(avgL(pLc[0], pDc[0], p6c[0], yA));
+            sA[5 * S + tid] = avgL(pLc[2], pDc[2], p6c[2], yA) + corrV1;
+            sA[6 * S + tid] = avgL(pLc[3], pDc[3], p6c[3], yA) + corrV2;
+            sA[7 * S + tid] = avgL(pLc[4], pDc[4], p6c[4], yA) + corrB1;
+            sA[8 * S + tid] = avgL(pLc[5], pDc[5], p6c[5], yA) + corrB2;
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R4
+    // face i+1/2 between this zone (L) and zone i+1 (R)
+    const bool face_ok = pen && i >= 3 && i <= M - 5;
+    T RPt = sA[0 * S + sp1], Ru = sA[1 * S + sp1], RC = sA[2 * S + sp1], Rk = sA[3 * S + sp1];
+    T Rr = sA[4 * S + sp1], Rv1 = sA[5 * S + sp1], Rv2 = sA[6 * S + sp1];
+    T Rb1 = sA[7 * S + sp1], Rb2 = sA[8 * S + sp1];
+    if (!face_ok) {  // keep unused lanes trivial (no Newton iterations)
+        RPt = LPt; Ru = Lu; RC = LC; Rk = Lk; Rr = Lr; Rv1 = Lv1; Rv2 = Lv2; Rb1 = Lb1; Rb2 = Lb2;
+    }
+    T Pst, ust;
+    {
+        const T Pd = T(0.5) * (bf1 * bf1 + bf2 * bf2);
+        const T PL = LPt + Pd, PR = RPt + Pd;
+        const T iPL = Ar<T>::rcp(PL), iPR = Ar<T>::rcp(PR);
+        const T Pfloor = T(1e-6) * tmin(PL, PR) - Pd;
+        const T tol = a.tol;
+        T P = LPt + LC * ((RPt - LPt) + RC * (Lu - Ru)) * Ar<T>::rcp(LC + RC);
+        P = tmax(P, Pfloor);
+        int it = 0;
+        bool conv = true;
+        T usL, usR, ZL, ZR, dP;
+        for (;;) {
+            T WL = LC * Ar<T>::sqrt_(T(1) + Lk * (P - LPt) * iPL);
+            T WR = RC * Ar<T>::sqrt_(T(1) + Rk * (P - RPt) * iPR);
+            usL = Lu - (P - LPt) * Ar<T>::rcp(WL);
+            usR = Ru + (P - RPt) * Ar<T>::rcp(WR);
+            ZL = T(2) * WL * WL * WL * Ar<T>::rcp(WL * WL + LC * LC);
+            ZR = T(2) * WR * WR * WR * Ar<T>::rcp(WR * WR + RC * RC);
+            dP = -ZL * ZR * (usR - usL) * Ar<T>::rcp(ZL + ZR);
+            if (tabs(dP) <= tol * (P + Pd)) break;
+            if (it >= a.max_iter) { conv = false; break; }
+            P = tmax(P + dP, Pfloor);
+            ++it;
+        }
+        Pst = tmax(P + dP, Pfloor);
+        ust = usL + ZR * (usR - usL) * Ar<T>::rcp(ZL + ZR);
+        if (STATS && a.stats) {
+            const bool counted = face_ok && g >= -1 && g <= N - 1;
+            // histogram of iteration counts: most faces take 0-2 iterations
+            int bin = it < 31 ? it : 31;
+            unsigned long long active = __ballot(counted);
+            while (active) {
+                int leader = __ffsll((long long)active) - 1;
+                int lb = __shfl(bin, leader);
+                unsigned long long same = __ballot(counted && bin == lb);
+                if (__lane_id() == leader) atomicAdd(&a.stats[lb], (unsigned long long)__popcll(same));
+                active &= ~same;
+            }
+            wave_count(&a.stats[33], counted && !conv);
+        }
+    }
+    // transverse pair: linear Alfven problem, increment form from the left
+    const T bns = T(0.5) * (bn + bnp);
+    const T Bns = bfn + bns;
+    const T sig = tsgn(Bns);
+    const T irs = Ar<T>::rcp(Lr + Rr);
+    const T v1s = Lv1 + (Rr * (Rv1 - Lv1) + sig * (Rb1 - Lb1)) * irs;
+    const T b1s = Lb1 + (Lr * (Rb1 - Lb1) + sig * Lr * Rr * (Rv1 - Lv1)) * irs;
+    const T v2s = Lv2 + (Rr * (Rv2 - Lv2) + sig * (Rb2 - Lb2)) * irs;
+    const T b2s = Lb2 + (Lr * (Rb2 - Lb2) + sig * Lr * Rr * (Rv2 - Lv2)) * irs;
+    // Lagrangian fluxes in dipole + deviation flux form
+    const T nn = bns * (bfn + T(0.5) * bns);
+    const T Fpi = Pst - nn;
+    const T Fv1 = -(Bns * b1s + bns * bf1);
+    const T Fv2 = -(Bns * b2s + bns * bf2);
+    const T Fb1 = ust * bf1 - Bns * v1s;
+    const T Fb2 = ust * bf2 - Bns * v2s;
+    const T Fe = ust * (Pst + nn) - Bns * (ust * bns + v1s * b1s + v2s * b2s);
+    const T delR = ust * dt;
+    if (slot_ok) {
+        sB[0 * S + tid] = Fpi;
+        sB[1 * S + tid] = Fv1;
+        sB[2 * S + tid] = Fv2;
+        sB[3 * S + tid] = Fb1;
+        sB[4 * S + tid] = Fb2;
+        sB[5 * S + tid] = Fe;
+        sB[6 * S + tid] = delR;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R5
+    // Lagrangian update of the zone contents (faces i-1/2, i+1/2)
+    const T delL = sB[6 * S + sm1];
+    T dC[7];
+    dC[0] = T(0);
+    dC[1] = -dt * (Fpi - sB[0 * S + sm1]);
+    dC[2] = -dt * (Fv1 - sB[1 * S + sm1]);
+    dC[3] = -dt * (Fv2 - sB[2 * S + sm1]);
+    dC[4] = -dt * (Fb1 - sB[3 * S + sm1]);
+    dC[5] = -dt * (Fb2 - sB[4 * S + sm1]);
+    dC[6] = -dt * (Fe - sB[5 * S + sm1]);
+    // remapped quantities per volume: rho, mn, m1, m2, b1, b2, E
+    const T Qr[7] = {Q[0], Q[1], Q[2], Q[3], Q[5], Q[6], Q[7]};
+    const T dd = delR - delL;
+    const T dVL = dxi + dd;
+    const T idVL = Ar<T>::rcp(dVL);
+    T QL[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) QL[k] = Qr[k] + (dC[k] - Qr[k] * dd) * idVL;
+    if (slot_ok) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) sA[k * S + tid] = QL[k];
+        sA[7 * S + tid] = dVL;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R6
+    T redgeR[7];
+    {
+        const T vm = sA[7 * S + sm1], vp = sA[7 * S + sp1], vp2 = sA[7 * S + sp2];
+        SlopeW<T> s0, s1;
+        s0.init(vm, dVL, vp);
+        s1.init(dVL, vp, vp2);
+        EdgeW<T> ew;
+        ew.init(vm, dVL, vp, vp2);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            T am = sA[k * S + sm1], ap = sA[k * S + sp1], ap2 = sA[k * S + sp2];
+            T da0 = s0.slope(am, QL[k], ap);
+            T da1 = s1.slope(QL[k], ap, ap2);
+            redgeR[k] = ew.edge(QL[k], ap, da0, da1);
+        }
+    }
+    if (slot_ok) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) sB[k * S + tid] = redgeR[k];
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R7
+    // donor-cell remap fluxes: this zone gives its right part across face
+    // i+1/2 when delta > 0 and its left part across i-1/2 when delta < 0
+    {
+        const bool zone_ok = pen && i >= 6 && i <= M - 7;
+        const bool wr = zone_ok && delR >= T(0);
+        const bool wl = zone_ok && delL < T(0) && i >= 1;
+        const T yR = delR * idVL, yL = -delL * idVL;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            T aL = sB[k * S + sm1];
+            T cL, cD, c6;
+            parabola(QL[k], aL, redgeR[k], fl, cL, cD, c6);
+            if (wr) sA[k * S + tid] = delR * avgR(cL, cD, c6, yR);
+            if (wl) sA[k * S + tid - d] = delL * avgL(cL, cD, c6, yL);
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ R8
+    double smax = 0.0;
+    if (interior) {
+        T out[8];
+        const T idx = Ar<T>::rcp(dxi);
+        T nw[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) nw[k] = Qr[k] + (dC[k] + sA[k * S + sm1] - sA[k * S + tid]) * idx;
+        T nbn = bn, nb1 = nw[4], nb2 = nw[5];
+        if (a.janhunen) {
+            // -v div B' source, split: n-derivative of B'_n, pre-sweep velocity
+            const T xm = a.xc[i - 1], xp = a.xc[i + 1];
+            const T divn = (bnp - bnm) * Ar<T>::rcp(xp - xm);
+            nbn -= dt * un * divn;
+            nb1 -= dt * v1 * divn;
+            nb2 -= dt * v2 * divn;
+        }
+        out[0] = nw[0];
+        out[1 + kn] = nw[1];
+        out[1 + k1] = nw[2];
+        out[1 + k2] = nw[3];
+        out[4 + kn] = nbn;
+        out[4 + k1] = nb1;
+        out[4 + k2] = nb2;
+        out[7] = nw[6];
+        bool masked = false;
+        if (a.has_inner) {
+            T x, y, z;
+            to_xyz<AX>(xci, c1, c2, x, y, z);
+            if (x * x + y * y + z * z < a.r_inner2) {
+                masked = true;
+                out[0] = a.inner_rho;
+                out[1] = out[2] = out[3] = T(0);
+                out[4] = out[5] = out[6] = T(0);
+                out[7] = a.inner_E;
+            }
+        }
+        T *uo = a.u + base + (long long)g * a.stride_n;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) uo[v * a.vol] = out[v];
+        if (FUSE_CFL && !masked) {
+            // signal speed of the updated zone (FP64), for the next step's dt
+            int ix, iy, iz;
+            if (AX == 0) { ix = g; iy = j1; iz = j2; }
+            else if (AX == 1) { iy = g; iz = j1; ix = j2; }
+            else { iz = g; ix = j1; iy = j2; }
+            double r_ = (double)out[0];
+            double vx = (double)out[1] / r_, vy = (double)out[2] / r_, vz = (double)out[3] / r_;
+            double px = (double)out[4], py = (double)out[5], pz = (double)out[6];
+            double p_ = ((double)gam - 1.0) * ((double)out[7] - 0.5 * r_ * (vx * vx + vy * vy + vz * vz) -
+                                                0.5 * (px * px + py * py + pz * pz));
+            if (p_ < (double)a.p_floor) p_ = (double)a.p_floor;
+            double Bx = px, By = py, Bz = pz;
+            if (a.has_bd) {
+                T bx, by, bz, x, y, z;
+                to_xyz<AX>(xci, c1, c2, x, y, z);
+                background(a, x, y, z, bx, by, bz);
+                Bx += (double)bx; By += (double)by; Bz += (double)bz;
+            }
+            double a2 = (double)gam * p_ / r_;
+            double b2 = (Bx * Bx + By * By + Bz * Bz) / r_;
+            const double ww[3] = {a.dxw_x[ix], a.dxw_y[iy], a.dxw_z[iz]};
+            const double vv[3] = {vx, vy, vz};
+            const double BB[3] = {Bx, By, Bz};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double ba2 = BB[c] * BB[c] / r_;
+                double disc = (a2 + b2) * (a2 + b2) - 4.0 * a2 * ba2;
+                disc = disc > 0.0 ? disc : 0.0;
+                double cf = __builtin_sqrt(0.5 * (a2 + b2 + __builtin_sqrt(disc)));
+                double s_ = (__builtin_fabs(vv[c]) + cf) / ww[c];
+                smax = s_ > smax ? s_ : smax;
+            }
+        }
+    }
+    if (FUSE_CFL) {
+        // wave max (all lanes active), workgroup max, one atomic per workgroup
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(smax, off);
+            smax = o > smax ? o : smax;
+        }
+        if (__lane_id() == 0) s_red[tid >> 6] = smax;
+        __syncthreads();
+        if (tid == 0) {
+            double m = 0.0;
+            const int nw = (blockDim.x + 63) >> 6;
+            for (int w = 0; w < nw; ++w) m = s_red[w] > m ? s_red[w] : m;
+            atomicMax(a.cfl_max, (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+}  // namespace ppmlr

@@ -1,0 +1,288 @@
+"""Python binding of the C ABI in include/ppmlr.h (ctypes; argument
+marshalling only -- every step of the sweep runs in the HIP library).
+
+PyTorch provides device memory and streams: a state is a contiguous CUDA
+(HIP) tensor of shape [8, nz, ny, nx], dtype float32 or float64, holding
+(rho, m_x, m_y, m_z, B'_x, B'_y, B'_z, E').
+
+The library must be built (``python -m paper_1607_02214_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppmlr.so")
+
+PPMLR_OK = 0
+PPMLR_EINVAL = -1
+PPMLR_ECFL = -2
+PPMLR_ERIEMANN = -3
+PPMLR_ENONPHYS = -4
+PPMLR_EDEVICE = -5
+PPMLR_ENOMEM = -6
+PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
+F32, F64 = 0, 1
+GHOSTS = 7
+
+_STATUS_NAMES = {0: "PPMLR_OK", -1: "PPMLR_EINVAL", -2: "PPMLR_ECFL", -3: "PPMLR_ERIEMANN",
+                 -4: "PPMLR_ENONPHYS", -5: "PPMLR_EDEVICE", -6: "PPMLR_ENOMEM"}
+
+
+class PPMLRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("flatten", C.c_int),
+        ("janhunen", C.c_int),
+        ("max_iter", C.c_int),
+        ("tol_f64", C.c_double),
+        ("tol_f32", C.c_double),
+        ("p_floor", C.c_double),
+        ("collect_stats", C.c_int),
+        ("debug_cfl", C.c_int),
+    ]
+
+
+class Grid(C.Structure):
+    _fields_ = [
+        ("n", C.c_int * 3),
+        ("bc_lo", C.c_int * 3),
+        ("bc_hi", C.c_int * 3),
+        ("r_inner", C.c_double),
+    ]
+
+
+class Coords(C.Structure):
+    _fields_ = [("faces", C.POINTER(C.c_double) * 3)]
+
+
+class State(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("dtype", C.c_int), ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("iters_hist", C.c_longlong * 32),
+        ("floor_hits", C.c_longlong),
+        ("nonconverged", C.c_longlong),
+        ("nonphys", C.c_longlong),
+    ]
+
+    def as_dict(self):
+        return {"iters_hist": list(self.iters_hist), "floor_hits": self.floor_hits,
+                "nonconverged": self.nonconverged, "nonphys": self.nonphys}
+
+
+# exported symbols and their signatures (mirrors include/ppmlr.h)
+_P = C.c_void_p
+_dp = C.POINTER(C.c_double)
+SIGNATURES = {
+    "ppmlr_default_options": (None, [C.POINTER(Options)]),
+    "ppmlr_create": (C.c_int, [C.POINTER(Grid), C.c_double, C.POINTER(Coords), C.POINTER(Options), C.POINTER(_P)]),
+    "ppmlr_destroy": (None, [_P]),
+    "ppmlr_last_error": (C.c_char_p, [_P]),
+    "ppmlr_set_dipole": (C.c_int, [_P, C.c_double, _dp]),
+    "ppmlr_set_background": (C.c_int, [_P, _dp]),
+    "ppmlr_set_inflow": (C.c_int, [_P, _dp]),
+    "ppmlr_set_inner": (C.c_int, [_P, C.c_double, C.c_double]),
+    "ppmlr_sweep": (C.c_int, [_P, C.POINTER(State), C.c_double, C.c_int]),
+    "ppmlr_step": (C.c_int, [_P, C.POINTER(State), C.c_double]),
+    "ppmlr_set_step_index": (C.c_int, [_P, C.c_longlong]),
+    "ppmlr_get_step_index": (C.c_int, [_P, C.POINTER(C.c_longlong)]),
+    "ppmlr_cfl_dt": (C.c_int, [_P, C.POINTER(State), C.c_double, _dp]),
+    "ppmlr_advance": (C.c_int, [_P, C.POINTER(State), C.c_int, C.c_double]),
+    "ppmlr_time": (C.c_int, [_P, C.POINTER(State), _dp]),
+    "ppmlr_totals": (C.c_int, [_P, C.POINTER(State), _dp]),
+    "ppmlr_stats": (C.c_int, [_P, _P, C.POINTER(Stats)]),
+    "ppmlr_reset_stats": (C.c_int, [_P, _P]),
+    "ppmlr_status_check": (C.c_int, [_P, _P]),
+    "ppmlr_set_profiling": (C.c_int, [_P, C.c_int]),
+    "ppmlr_kernel_times": (C.c_int, [_P, _dp, C.POINTER(C.c_longlong)]),
+    "ppmlr_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
+    "ppmlr_get_tile": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().ppmlr_default_options(C.byref(o))
+    return o
+
+
+def _d3(v):
+    return (C.c_double * 3)(*[float(x) for x in v])
+
+
+class Context:
+    """Owns one ppmlr_ctx (grid tables, counters, device scalars)."""
+
+    def __init__(self, faces, bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3, gamma=5.0 / 3.0,
+                 r_inner=0.0, options: Options | None = None, **opt_overrides):
+        self._faces = [np.ascontiguousarray(f, dtype=np.float64) for f in faces]
+        g = Grid()
+        cd = Coords()
+        for a in range(3):
+            g.n[a] = len(self._faces[a]) - 1
+            g.bc_lo[a] = int(bc_lo[a])
+            g.bc_hi[a] = int(bc_hi[a])
+            cd.faces[a] = self._faces[a].ctypes.data_as(_dp)
+        g.r_inner = float(r_inner)
+        opt = options if options is not None else default_options()
+        for k, v in opt_overrides.items():
+            setattr(opt, k, v)
+        self.options = opt
+        self.n = tuple(g.n)
+        h = _P()
+        rc = lib().ppmlr_create(C.byref(g), float(gamma), C.byref(cd), C.byref(opt), C.byref(h))
+        if rc != PPMLR_OK:
+            raise PPMLRError(rc, "ppmlr_create rejected the grid or options")
+        self.h = h
+
+    # -- helpers
+    def _chk(self, rc):
+        if rc != PPMLR_OK:
+            msg = lib().ppmlr_last_error(self.h)
+            raise PPMLRError(rc, msg.decode() if msg else "")
+        return rc
+
+    @staticmethod
+    def state(u, stream=None) -> State:
+        import torch
+        if not u.is_cuda or not u.is_contiguous():
+            raise ValueError("state must be a contiguous device tensor")
+        if u.dtype == torch.float32:
+            dt = F32
+        elif u.dtype == torch.float64:
+            dt = F64
+        else:
+            raise ValueError("state dtype must be float32 or float64")
+        if stream is None:
+            stream = torch.cuda.current_stream(u.device).cuda_stream
+        return State(C.c_void_p(u.data_ptr()), dt, C.c_void_p(stream))
+
+    def _st(self, u, stream):
+        if tuple(u.shape) != (8, self.n[2], self.n[1], self.n[0]):
+            raise ValueError(f"state shape {tuple(u.shape)} does not match the grid {self.n}")
+        return self.state(u, stream)
+
+    # -- ABI wrappers (same names without the prefix)
+    def set_dipole(self, moment, direction=(0.0, 0.0, -1.0)):
+        return self._chk(lib().ppmlr_set_dipole(self.h, float(moment), _d3(direction)))
+
+    def set_background(self, b):
+        return self._chk(lib().ppmlr_set_background(self.h, _d3(b)))
+
+    def set_inflow(self, prim):
+        arr = (C.c_double * 8)(*[float(x) for x in prim])
+        return self._chk(lib().ppmlr_set_inflow(self.h, arr))
+
+    def set_inner(self, rho, p):
+        return self._chk(lib().ppmlr_set_inner(self.h, float(rho), float(p)))
+
+    def sweep(self, u, dt, axis, stream=None):
+        st = self._st(u, stream)
+        return self._chk(lib().ppmlr_sweep(self.h, C.byref(st), float(dt), int(axis)))
+
+    def step(self, u, dt, stream=None):
+        st = self._st(u, stream)
+        return self._chk(lib().ppmlr_step(self.h, C.byref(st), float(dt)))
+
+    def set_step_index(self, k):
+        return self._chk(lib().ppmlr_set_step_index(self.h, int(k)))
+
+    def get_step_index(self):
+        v = C.c_longlong()
+        self._chk(lib().ppmlr_get_step_index(self.h, C.byref(v)))
+        return v.value
+
+    def cfl_dt(self, u, cfl, stream=None):
+        st = self._st(u, stream)
+        out = C.c_double()
+        self._chk(lib().ppmlr_cfl_dt(self.h, C.byref(st), float(cfl), C.byref(out)))
+        return out.value
+
+    def advance(self, u, nsteps, cfl, stream=None):
+        st = self._st(u, stream)
+        return self._chk(lib().ppmlr_advance(self.h, C.byref(st), int(nsteps), float(cfl)))
+
+    def time(self, u=None, stream=None):
+        out = C.c_double()
+        st = self._st(u, stream) if u is not None else None
+        self._chk(lib().ppmlr_time(self.h, C.byref(st) if st is not None else None, C.byref(out)))
+        return out.value
+
+    def totals(self, u, stream=None):
+        st = self._st(u, stream)
+        out = (C.c_double * 8)()
+        self._chk(lib().ppmlr_totals(self.h, C.byref(st), out))
+        return np.array(out[:])
+
+    def stats(self, stream=None):
+        s = Stats()
+        self._chk(lib().ppmlr_stats(self.h, C.c_void_p(stream) if stream else None, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self, stream=None):
+        return self._chk(lib().ppmlr_reset_stats(self.h, C.c_void_p(stream) if stream else None))
+
+    def status_check(self, stream=None) -> int:
+        """Returns the status code (does not raise)."""
+        return lib().ppmlr_status_check(self.h, C.c_void_p(stream) if stream else None)
+
+    def set_profiling(self, enable=True):
+        return self._chk(lib().ppmlr_set_profiling(self.h, int(bool(enable))))
+
+    def kernel_times(self):
+        ms = (C.c_double * 3)()
+        n = (C.c_longlong * 3)()
+        self._chk(lib().ppmlr_kernel_times(self.h, ms, n))
+        return list(ms), list(n)
+
+    def set_tile(self, axis, pencils):
+        return self._chk(lib().ppmlr_set_tile(self.h, int(axis), int(pencils)))
+
+    def get_tile(self, axis, dtype=F32):
+        v = C.c_int()
+        self._chk(lib().ppmlr_get_tile(self.h, int(axis), int(dtype), C.byref(v)))
+        return v.value
+
+    def last_error(self):
+        m = lib().ppmlr_last_error(self.h)
+        return m.decode() if m else ""
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ppmlr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
