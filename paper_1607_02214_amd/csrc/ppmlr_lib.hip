@@ -18,6 +18,7 @@ using ppmlr::kG;
 using ppmlr::kSlotsA;
 using ppmlr::kSlotsB;
 using ppmlr::kStatWords;
+using ppmlr::kStatSlots;
 
 struct AxisTables {
     // FP64 and FP32 copies: extended widths [M], centres [M], faces [M+1];
@@ -38,7 +39,7 @@ struct ppmlr_ctx {
     double dip_m = 0.0, dir[3] = {0.0, 0.0, -1.0}, bext[3] = {0.0, 0.0, 0.0};
     double inflow[8] = {1, 0, 0, 0, 0, 0, 0, 1};
     double inner_rho = 1.0, inner_p = 1.0;
-    unsigned long long *d_stats = nullptr;   // kStatWords
+    unsigned long long *d_stats = nullptr;   // kStatSlots x kStatWords
     unsigned long long *d_cflmax = nullptr;  // signal-speed max (double bits)
     double *d_dt = nullptr;                  // device-resident dt
     double *d_time = nullptr;                // accumulated simulated time
@@ -149,8 +150,9 @@ int auto_tile(const ppmlr_ctx *c, int axis, int elem)
     for (int P = 1; P <= 16; ++P) {
         int thr = block_threads(P, M);
         if (thr > cap && P > 1) break;
-        size_t lds = (size_t)(kSlotsA + kSlotsB) * P * M * elem;
-        if (lds > 160 * 1024) break;
+        int sm = thr <= 256 ? 256 : (thr <= 512 ? 512 : 1024);
+        size_t lds = (size_t)(kSlotsA + kSlotsB) * sm * elem;
+        if (lds > 160 * 1024 && (elem == 4 || P > 1)) break;
         int tiles_q = (nq + P - 1) / P;
         double cost = (double)thr * tiles_q / ((double)N * nq);  // lanes per useful zone
         if (cost < best_cost - 1e-9) { best_cost = cost; best = P; }
@@ -228,13 +230,13 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     a.xcw_x = c->tab[0].xci64; a.xcw_y = c->tab[1].xci64; a.xcw_z = c->tab[2].xci64;
 }
 
-template <int AX, typename T, bool STATS, bool FUSE, int LB>
+template <int AX, typename T, bool STATS, bool FUSE, int SM>
 ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
 {
     const int threads = block_threads(a.P, a.M);
-    const size_t lds = (size_t)(kSlotsA + kSlotsB) * a.S * sizeof(T);
+    const size_t lds = (size_t)(kSlotsA + kSlotsB) * (SM > 0 ? SM : a.S) * sizeof(T);
     const int blocks = 8 * a.tiles_per_xcd;
-    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, LB>;
+    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute");
@@ -243,18 +245,37 @@ ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t 
     return hip_check(c, hipGetLastError(), "sweep launch");
 }
 
+// LDS stride of a launch: the smallest power of two >= the workgroup size
+// (256, 512, 1024) whose buffers fit the LDS; FP64 tiles above 512 threads use
+// the exact runtime stride instead.
+template <typename T>
+int lds_stride(int threads)
+{
+    int sm = threads <= 256 ? 256 : (threads <= 512 ? 512 : 1024);
+    if ((size_t)(kSlotsA + kSlotsB) * sm * sizeof(T) > 160 * 1024) return 0;
+    return sm;
+}
+
+template <int AX, typename T, bool STATS, bool FUSE>
+ppmlr_status launch_sm(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
+{
+    switch (lds_stride<T>(block_threads(a.P, a.M))) {
+    case 256: return launch_one<AX, T, STATS, FUSE, 256>(c, a, st);
+    case 512: return launch_one<AX, T, STATS, FUSE, 512>(c, a, st);
+    case 1024:
+        if constexpr (sizeof(T) == 4) return launch_one<AX, T, STATS, FUSE, 1024>(c, a, st);
+        else return launch_one<AX, T, STATS, FUSE, 0>(c, a, st);
+    default:
+        if constexpr (sizeof(T) == 8) return launch_one<AX, T, STATS, FUSE, 0>(c, a, st);
+        else return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
+    }
+}
+
 template <int AX, typename T>
 ppmlr_status launch_axis(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st, bool stats, bool fuse)
 {
-    const bool big = block_threads(a.P, a.M) > 512;
-#define PPMLR_L(S_, F_)                                                         \
-    return big ? launch_one<AX, T, S_, F_, 1024>(c, a, st) : launch_one<AX, T, S_, F_, 512>(c, a, st);
-    if (stats) {
-        if (fuse) { PPMLR_L(true, true) } else { PPMLR_L(true, false) }
-    } else {
-        if (fuse) { PPMLR_L(false, true) } else { PPMLR_L(false, false) }
-    }
-#undef PPMLR_L
+    if (stats) return fuse ? launch_sm<AX, T, true, true>(c, a, st) : launch_sm<AX, T, true, false>(c, a, st);
+    return fuse ? launch_sm<AX, T, false, true>(c, a, st) : launch_sm<AX, T, false, false>(c, a, st);
 }
 
 template <typename T>
@@ -559,13 +580,14 @@ ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coor
         if (!s) s = upload(c, &t.xci32, xci);
     }
     c->partial_blocks = kTotBlocks;
-    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_stats, sizeof(unsigned long long) * kStatWords), "hipMalloc");
+    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_stats, sizeof(unsigned long long) * kStatWords * kStatSlots),
+                          "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_cflmax, sizeof(unsigned long long)), "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_dt, sizeof(double)), "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_time, sizeof(double)), "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_partials, sizeof(double) * (8 * kTotBlocks + 8)), "hipMalloc");
     if (!s) {
-        hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_stats, kStatWords);
+        hipLaunchKernelGGL(clear_u64, dim3(1), dim3(256), 0, (hipStream_t)0, c->d_stats, kStatWords * kStatSlots);
         hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_cflmax, 1);
         hipLaunchKernelGGL(clear_f64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_dt, 1);
         hipLaunchKernelGGL(clear_f64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_time, 1);
@@ -785,11 +807,15 @@ ppmlr_status ppmlr_totals(ppmlr_ctx *c, const ppmlr_state *s, double out[8])
 ppmlr_status ppmlr_stats(ppmlr_ctx *c, void *stream, ppmlr_stats_t *out)
 {
     if (!c || !out) return PPMLR_EINVAL;
-    unsigned long long h[kStatWords];
+    std::vector<unsigned long long> raw((size_t)kStatWords * kStatSlots);
     hipStream_t st = (hipStream_t)stream;
-    ppmlr_status e = hip_check(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    ppmlr_status e = hip_check(c, hipMemcpyAsync(raw.data(), c->d_stats, sizeof(unsigned long long) * raw.size(),
+                                                 hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
     if (e) return e;
+    unsigned long long h[kStatWords] = {0};
+    for (int sl = 0; sl < kStatSlots; ++sl)
+        for (int k = 0; k < kStatWords; ++k) h[k] += raw[(size_t)sl * kStatWords + k];
     for (int b = 0; b < 32; ++b) out->iters_hist[b] = (long long)h[b];
     out->floor_hits = (long long)h[32];
     out->nonconverged = (long long)h[33];
@@ -800,7 +826,7 @@ ppmlr_status ppmlr_stats(ppmlr_ctx *c, void *stream, ppmlr_stats_t *out)
 ppmlr_status ppmlr_reset_stats(ppmlr_ctx *c, void *stream)
 {
     if (!c) return PPMLR_EINVAL;
-    hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_stats, kStatWords);
+    hipLaunchKernelGGL(clear_u64, dim3(1), dim3(256), 0, (hipStream_t)stream, c->d_stats, kStatWords * kStatSlots);
     return hip_check(c, hipGetLastError(), "reset stats");
 }
 

@@ -29,6 +29,7 @@ constexpr int kG = 7;           // ghost zones per side
 constexpr int kSlotsA = 14;     // values per zone in LDS buffer A
 constexpr int kSlotsB = 8;      // values per zone in LDS buffer B
 constexpr int kStatWords = 35;  // iteration histogram [32], floors, nonconverged, nonphys
+constexpr int kStatSlots = 64;  // copies of the counters (workgroup b adds to copy b % 64)
 
 enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
 
@@ -77,7 +78,7 @@ struct SweepArgs {
     int has_inner;
     int flatten, janhunen, max_iter;
     T tol, p_floor;
-    unsigned long long *stats;  // kStatWords counters or nullptr
+    unsigned long long *stats;  // kStatSlots x kStatWords counters or nullptr
     unsigned long long *cfl_max;// fused signal-speed max (double bits) or nullptr
     const double *dxw_x, *dxw_y, *dxw_z;  // FP64 interior widths of all axes (fused CFL)
     const double *xcw_x, *xcw_y, *xcw_z;  // FP64 interior centres of all axes (fused CFL)
@@ -131,53 +132,57 @@ __device__ inline void field_at(const SweepArgs<T> &a, T n, T c1, T c2, T &bn, T
 
 // Edge value a_{j+1/2} on nonuniform widths w0..w3 = w_{j-1..j+2}
 // (Colella & Woodward 1984, Eq. 1.6) from the (limited) slopes of zones j
-// and j+1; the width weights are shared by all variables of a face.
+// and j+1.  The width weights are shared by all variables of a face and
+// folded into three coefficients: a_j + E0 (a_{j+1} - a_j) + E2 da_{j+1} + E3 da_j.
 template <typename T>
 struct EdgeW {
-    T e0, t1, t2, t3, inv4;
+    T E0, E2, E3;
     __device__ inline void init(T w0, T w1, T w2, T w3)
     {
-        T s12 = w1 + w2;
-        T i12 = Ar<T>::rcp(s12);
-        T d1 = T(2) * w1 + w2;
-        T d2 = w1 + T(2) * w2;
-        T id1 = Ar<T>::rcp(d1);
-        T id2 = Ar<T>::rcp(d2);
-        e0 = w1 * i12;
-        t1 = T(2) * w2 * w1 * i12 * ((w0 + w1) * id1 - (w3 + w2) * id2);
-        t2 = -w1 * (w0 + w1) * id1;
-        t3 = w2 * (w2 + w3) * id2;
-        inv4 = Ar<T>::rcp(w0 + w1 + w2 + w3);
+        T i12 = Ar<T>::rcp(w1 + w2);
+        T id1 = Ar<T>::rcp(T(2) * w1 + w2);
+        T id2 = Ar<T>::rcp(w1 + T(2) * w2);
+        T inv4 = Ar<T>::rcp(w0 + w1 + w2 + w3);
+        T t1 = T(2) * w2 * w1 * i12 * ((w0 + w1) * id1 - (w3 + w2) * id2);
+        E0 = w1 * i12 + t1 * inv4;
+        E2 = -w1 * (w0 + w1) * id1 * inv4;
+        E3 = w2 * (w2 + w3) * id2 * inv4;
     }
     __device__ inline T edge(T aj, T ajp, T daj, T dajp) const
     {
-        T d = ajp - aj;
-        return aj + e0 * d + (t1 * d + t2 * dajp + t3 * daj) * inv4;
+        return aj + E0 * (ajp - aj) + E2 * dajp + E3 * daj;
     }
 };
 
 // Average slope times width in zone j on widths wm, w0, wp (CW84 Eq. 1.7),
-// then limited (Eq. 1.8).
+// da = A (a_{j+1} - a_j) + B (a_j - a_{j-1}), limited by Eq. 1.8.  When the
+// two one-sided differences share a sign, da shares it too (A, B > 0), so
+// sgn(da) min(|da|, 2|dm|, 2|dp|) = sgn(dp) 2 min(|da|/2, |dm|, |dp|).
 template <typename T>
 struct SlopeW {
-    T cs, cp, cm;
+    T A, B;
     __device__ inline void init(T wm, T w0, T wp)
     {
-        cs = w0 * Ar<T>::rcp(wm + w0 + wp);
-        cp = (T(2) * wm + w0) * Ar<T>::rcp(wp + w0);
-        cm = (w0 + T(2) * wp) * Ar<T>::rcp(wm + w0);
+        T cs = w0 * Ar<T>::rcp(wm + w0 + wp);
+        A = cs * (T(2) * wm + w0) * Ar<T>::rcp(wp + w0);
+        B = cs * (w0 + T(2) * wp) * Ar<T>::rcp(wm + w0);
     }
     __device__ inline T slope(T am, T a0, T ap) const
     {
         T dp = ap - a0;
         T dm = a0 - am;
-        T da = cs * (cp * dp + cm * dm);
-        if (dp * dm > T(0)) {
-            T m = tmin(tabs(da), tmin(T(2) * tabs(dm), T(2) * tabs(dp)));
-            return da < T(0) ? -m : (da > T(0) ? m : T(0));
-        }
-        return T(0);
+        T da = A * dp + B * dm;
+        T m = __builtin_fmin(__builtin_fmin(__builtin_fabs(T(0.5) * da), __builtin_fabs(dm)), __builtin_fabs(dp));
+        T r = __builtin_copysign(m + m, dp);
+        return (dp * dm > T(0)) ? r : T(0);
     }
+};
+
+// Domain-of-dependence fraction y with its two shared coefficients.
+template <typename T>
+struct Frac {
+    T h, c;   // y/2 and 1 - 2y/3
+    __device__ inline explicit Frac(T y) : h(T(0.5) * y), c(T(1) - (T(2) / T(3)) * y) {}
 };
 
 // Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity.
@@ -203,34 +208,47 @@ __device__ inline void parabola(T a, T aL, T aR, T f, T &oL, T &oD, T &o6)
 // Averages of a zone parabola over the fraction y next to its right edge
 // (avgR) or left edge (avgL) (CW84 Eq. 1.12).
 template <typename T>
-__device__ inline T avgR(T aL, T dA, T a6, T y)
+__device__ inline T avgR(T aL, T dA, T a6, const Frac<T> &f)
 {
-    return (aL + dA) - T(0.5) * y * (dA - (T(1) - (T(2) / T(3)) * y) * a6);
+    return (aL + dA) - f.h * (dA - f.c * a6);
 }
 template <typename T>
-__device__ inline T avgL(T aL, T dA, T a6, T y)
+__device__ inline T avgL(T aL, T dA, T a6, const Frac<T> &f)
 {
-    return aL + T(0.5) * y * (dA + (T(1) - (T(2) / T(3)) * y) * a6);
+    return aL + f.h * (dA + f.c * a6);
 }
 
-// Wave-level counter update: one atomic per wave and non-empty bin.
-__device__ inline void wave_count(unsigned long long *ctr, bool pred)
+// Counter update aggregated per wave: the lowest active lane of each group of
+// lanes with the same bin adds the group's population to the workgroup's LDS
+// counters (flushed to global memory once per workgroup).
+__device__ inline void wave_add(unsigned int *s_ctr, bool pred)
 {
     unsigned long long m = __ballot(pred);
-    if (m != 0ull) {
-        int lane = __lane_id();
-        unsigned long long lower = m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-        if (pred && lower == 0ull) atomicAdd(ctr, (unsigned long long)__popcll(m));
+    if (m != 0ull && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(s_ctr, (unsigned int)__popcll(m));
+}
+__device__ inline void wave_hist(unsigned int *s_hist, bool counted, int bin)
+{
+    unsigned long long active = __ballot(counted);
+    while (active) {
+        int leader = __ffsll((long long)active) - 1;
+        int lb = __shfl(bin, leader);
+        unsigned long long same = __ballot(counted && bin == lb);
+        if (__lane_id() == leader) atomicAdd(&s_hist[lb], (unsigned int)__popcll(same));
+        active &= ~same;
     }
 }
 
-template <int AX, typename T, bool STATS, bool FUSE_CFL, int LB>
-__global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
+// SM: LDS stride per stored value (a power of two >= P*M, so that every LDS
+// access uses an immediate offset), or 0 for a runtime stride P*M.
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
+__global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int S = SM > 0 ? SM : a.S;                      // LDS stride
     T *sA = reinterpret_cast<T *>(smem_raw);
-    T *sB = sA + kSlotsA * a.S;
+    T *sB = sA + kSlotsA * S;
     __shared__ double s_red[16];
+    __shared__ unsigned int s_stat[kStatWords];
 
     // XCD-aware tile order: consecutive workgroups go to different XCDs
     // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
@@ -243,8 +261,9 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
     const int q0 = tq * a.P;
 
     const int tid = threadIdx.x;
-    const int S = a.S, M = a.M, N = a.N, P = a.P;
-    const bool slot_ok = tid < S;
+    if (STATS && tid < kStatWords) s_stat[tid] = 0u;   // ordered by the first barrier
+    const int Suse = a.S, M = a.M, N = a.N, P = a.P;
+    const bool slot_ok = tid < Suse;
     int p, i;
     if (AX == 0) { p = tid / M; i = tid - p * M; }       // zones of a pencil adjacent
     else { i = tid / P; p = tid - i * P; }                // pencils adjacent (coalesced)
@@ -253,7 +272,7 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
     const bool pen = slot_ok && q < a.nq;
     const int g = i - kG;                                 // zone index along the pencil
     const bool interior = pen && g >= 0 && g < N;
-    const int tsafe = slot_ok ? tid : S - 1;              // padding lanes read a valid slot
+    const int tsafe = slot_ok ? tid : Suse - 1;           // padding lanes read a valid slot
     auto nb = [&](int k) -> int {                         // slot of zone i+k (clamped)
         int ii = i + k;
         return (ii >= 0 && ii < M && slot_ok) ? tid + k * d : tsafe;
@@ -335,11 +354,8 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
     const T dm = rho * dxi;
     const T Pt = pth + bd1 * b1 + bd2 * b2 + T(0.5) * (b1 * b1 + b2 * b2);
     const T Pa = Pt + T(0.5) * (bd1 * bd1 + bd2 * bd2);
-    if (STATS && a.stats) {
-        bool bad = interior && (!(rho > T(0)) || !__builtin_isfinite(rho) || !__builtin_isfinite(Q[7]));
-        wave_count(&a.stats[32], interior && floored);
-        wave_count(&a.stats[34], bad);
-    }
+    const bool cnt_floor = interior && floored;
+    const bool cnt_bad = interior && (!(rho > T(0)) || !__builtin_isfinite(rho) || !__builtin_isfinite(Q[7]));
     // primitive set used for reconstruction: rho, u, v1, v2, b1, b2, p
     const T W[7] = {rho, un, v1, v2, b1, b2, pth};
     if (slot_ok) {
@@ -411,8 +427,8 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
     const T Cn = Ar<T>::sqrt_(rho * (gam * pth + Bt1c * Bt1c + Bt2c * Bt2c));
     const T CA = Ar<T>::sqrt_(rho) * tabs(Bnc);
     const T idm = Ar<T>::rcp(dm);
-    const T yn = tmin(T(1), Cn * dt * idm);
-    const T yA = tmin(T(1), CA * dt * idm);
+    const Frac<T> yn(tmin(T(1), Cn * dt * idm));
+    const Frac<T> yA(tmin(T(1), CA * dt * idm));
     // time-centring of the couplings left out of the two decoupled Riemann
     // problems: oblique-field terms and the variation of B_n along the pencil
     const T hdt = T(0.5) * dt;
@@ -520,19 +536,14 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
         }
         Pst = tmax(P + dP, Pfloor);
         ust = usL + ZR * (usR - usL) * Ar<T>::rcp(ZL + ZR);
-        if (STATS && a.stats) {
+        if (STATS) {
+            // faces -1/2 .. N-1/2 of the pencil: iteration histogram and
+            // non-converged count; zone counters of R1 (after the first barrier)
             const bool counted = face_ok && g >= -1 && g <= N - 1;
-            // histogram of iteration counts: most faces take 0-2 iterations
-            int bin = it < 31 ? it : 31;
-            unsigned long long active = __ballot(counted);
-            while (active) {
-                int leader = __ffsll((long long)active) - 1;
-                int lb = __shfl(bin, leader);
-                unsigned long long same = __ballot(counted && bin == lb);
-                if (__lane_id() == leader) atomicAdd(&a.stats[lb], (unsigned long long)__popcll(same));
-                active &= ~same;
-            }
-            wave_count(&a.stats[33], counted && !conv);
+            wave_hist(s_stat, counted, it < 31 ? it : 31);
+            wave_add(&s_stat[33], counted && !conv);
+            wave_add(&s_stat[32], cnt_floor);
+            wave_add(&s_stat[34], cnt_bad);
         }
     }
     // transverse pair: linear Alfven problem, increment form from the left
@@ -620,7 +631,7 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
         const bool zone_ok = pen && i >= 6 && i <= M - 7;
         const bool wr = zone_ok && delR >= T(0);
         const bool wl = zone_ok && delL < T(0) && i >= 1;
-        const T yR = delR * idVL, yL = -delL * idVL;
+        const Frac<T> yR(delR * idVL), yL(-delL * idVL);
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
             T aL = sB[k * S + sm1];
@@ -706,6 +717,11 @@ __global__ void __launch_bounds__(LB) sweep_kernel(const SweepArgs<T> a)
                 smax = s_ > smax ? s_ : smax;
             }
         }
+    }
+    if (STATS) {
+        __syncthreads();
+        if (tid < kStatWords && s_stat[tid] != 0u && a.stats)
+            atomicAdd(&a.stats[(b % kStatSlots) * kStatWords + tid], (unsigned long long)s_stat[tid]);
     }
     if (FUSE_CFL) {
         // wave max (all lanes active), workgroup max, one atomic per workgroup

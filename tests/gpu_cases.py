@@ -107,3 +107,25 @@ def normwise_errors(gpu: np.ndarray, ref: np.ndarray):
 def log(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def fp32_errors(gpu: np.ndarray, ref: np.ndarray, gamma=5.0 / 3.0):
+    """FP32-vs-FP64 error per result: normwise on the primitive fields rho,
+    p and |B'| (max |f32 - f64| / max |f64|), and the momentum error measured
+    against the flow's momentum scale max(rho * c) with c the magnetosonic
+    speed sqrt((gamma p + |B'|^2) / rho)."""
+    def prim(U):
+        U = U.reshape(8, -1).astype(np.float64)
+        rho = U[0]
+        v2 = (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / (rho * rho)
+        b2 = U[4] ** 2 + U[5] ** 2 + U[6] ** 2
+        p = (gamma - 1) * (U[7] - 0.5 * rho * v2 - 0.5 * b2)
+        return rho, p, np.sqrt(b2), U[1:4]
+    rg, pg, bg, mg = prim(gpu)
+    rr, pr, br, mr = prim(ref)
+    out = {}
+    for name, a, b in (("rho", rg, rr), ("p", pg, pr), ("|B'|", bg, br)):
+        out[name] = float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+    mscale = np.max(np.sqrt(rr * (gamma * pr + br * br)))
+    out["m"] = float(np.max(np.abs(mg - mr)) / mscale)
+    return out
