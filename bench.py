@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -127,6 +129,8 @@ def main():
     def run(dtype, steps, warmup, profile=True):
         ctx = make_ctx()
         u = torch.from_numpy(setup.U).to(device="cuda", dtype=dtype).contiguous()
+        tiles = ctx.autotune(u, reps=3)          # tile search (outside the timed region)
+        print(f"[bench] autotuned tiles {tiles}", file=sys.stderr, flush=True)
         ctx.advance(u, warmup, args.cfl)
         torch.cuda.synchronize()
         ctx.reset_stats()
@@ -146,6 +150,15 @@ def main():
         finite = bool(torch.isfinite(u).all().item())
         return ctx, u, ms, wall, kms, kn, status, st, finite
 
+    if args.copy_calibration:
+        # plain device-to-device copy of exactly 1 GiB: its FETCH_SIZE and
+        # WRITE_SIZE readings give the counter-to-byte scale
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] fp32: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
     ctx, u, ms, wall, kms, kn, status, st, finite = run(torch.float32, args.steps, args.warmup)
     value = zones * args.steps / (ms / 1000.0)

@@ -166,6 +166,12 @@ ppmlr_status ppmlr_kernel_times(ppmlr_ctx *ctx, double ms[3], long long launches
 ppmlr_status ppmlr_set_tile(ppmlr_ctx *ctx, int axis, int pencils);
 ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *pencils);
 
+/* Tile autotuner: for each axis, times `reps` sweeps of every tile shape that
+ * fits one workgroup on a library-owned copy of the state (the caller's state
+ * is not modified), keeps the fastest per axis and returns them in tiles[3]
+ * (may be NULL).  Synchronises; allocates and frees one state-sized buffer. */
+ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, int tiles[3]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -853,6 +853,60 @@ ppmlr_status ppmlr_set_tile(ppmlr_ctx *c, int axis, int pencils)
     return PPMLR_OK;
 }
 
+ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int tiles[3])
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (reps < 1) return fail(c, PPMLR_EINVAL, "reps must be >= 1");
+    const size_t elem = s->dtype == PPMLR_F64 ? 8 : 4;
+    const size_t bytes = (size_t)8 * c->n[0] * c->n[1] * c->n[2] * elem;
+    hipStream_t st = (hipStream_t)s->stream;
+    double dt = 0.0;
+    e = ppmlr_cfl_dt(c, s, 0.2, &dt);
+    if (e) return e;
+    void *scratch = nullptr;
+    e = hip_check(c, hipMalloc(&scratch, bytes), "hipMalloc");
+    if (e) return e;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (!e) e = hip_check(c, hipEventCreate(&t0), "hipEventCreate");
+    if (!e) e = hip_check(c, hipEventCreate(&t1), "hipEventCreate");
+    const bool prof = c->profiling;
+    c->profiling = false;
+    ppmlr_state tmp = *s;
+    tmp.u = scratch;
+    for (int axis = 0; axis < 3 && !e; ++axis) {
+        const int M = c->n[axis] + 2 * kG;
+        int best = 1;
+        float best_ms = 1e30f;
+        for (int P = 1; P <= 32 && !e; ++P) {
+            const int thr = block_threads(P, M);
+            if (thr > 1024) break;
+            const int sm = thr <= 256 ? 256 : (thr <= 512 ? 512 : 1024);
+            if ((size_t)(kSlotsA + kSlotsB) * sm * elem > 160 * 1024 && !(elem == 8 && thr > 512 &&
+                (size_t)(kSlotsA + kSlotsB) * P * M * elem <= 160 * 1024))
+                continue;
+            c->tile[axis] = P;
+            e = hip_check(c, hipMemcpyAsync(scratch, s->u, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+            if (!e) e = do_sweep(c, &tmp, dt, nullptr, axis, false);   // warm-up
+            if (!e) e = hip_check(c, hipEventRecord(t0, st), "hipEventRecord");
+            for (int r = 0; r < reps && !e; ++r) e = do_sweep(c, &tmp, dt, nullptr, axis, false);
+            if (!e) e = hip_check(c, hipEventRecord(t1, st), "hipEventRecord");
+            if (!e) e = hip_check(c, hipEventSynchronize(t1), "hipEventSynchronize");
+            float ms = 0.0f;
+            if (!e) e = hip_check(c, hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+            if (!e && ms < best_ms) { best_ms = ms; best = P; }
+        }
+        c->tile[axis] = best;
+        if (tiles) tiles[axis] = best;
+    }
+    c->profiling = prof;
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(scratch);
+    return e;
+}
+
 ppmlr_status ppmlr_get_tile(const ppmlr_ctx *c, int axis, int dtype, int *pencils)
 {
     if (!c || axis < 0 || axis > 2 || !pencils) return PPMLR_EINVAL;

@@ -185,24 +185,25 @@ struct Frac {
     __device__ inline explicit Frac(T y) : h(T(0.5) * y), c(T(1) - (T(2) / T(3)) * y) {}
 };
 
-// Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity.
+// Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity
+// (written with selects: at a local extremum both edges take the zone
+// average; otherwise the edge on the far side of an overshooting parabola is
+// moved so that the parabola stays monotone).
 template <typename T>
 __device__ inline void parabola(T a, T aL, T aR, T f, T &oL, T &oD, T &o6)
 {
     aL = aL + f * (a - aL);
     aR = aR + f * (a - aR);
-    if ((aR - a) * (a - aL) <= T(0)) {
-        aL = a;
-        aR = a;
-    } else {
-        T dA = aR - aL;
-        T a6 = T(6) * (a - T(0.5) * (aL + aR));
-        if (dA * a6 > dA * dA) aL = T(3) * a - T(2) * aR;
-        else if (-dA * dA > dA * a6) aR = T(3) * a - T(2) * aL;
-    }
-    oL = aL;
-    oD = aR - aL;
-    o6 = T(6) * (a - T(0.5) * (aL + aR));
+    const T dA = aR - aL;
+    const T a6 = T(6) * (a - T(0.5) * (aL + aR));
+    const bool ext = (aR - a) * (a - aL) <= T(0);
+    const bool fixL = dA * a6 > dA * dA;
+    const bool fixR = !fixL && (-dA * dA > dA * a6);
+    const T nL = ext ? a : (fixL ? T(3) * a - T(2) * aR : aL);
+    const T nR = ext ? a : (fixR ? T(3) * a - T(2) * aL : aR);
+    oL = nL;
+    oD = nR - nL;
+    o6 = T(6) * (a - T(0.5) * (nL + nR));
 }
 
 // Averages of a zone parabola over the fraction y next to its right edge
@@ -520,22 +521,27 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
         P = tmax(P, Pfloor);
         int it = 0;
         bool conv = true;
-        T usL, usR, ZL, ZR, dP;
+        // The velocity mismatch u*_R - u*_L is formed from differences
+        // ((u_R - u_L) + jumps / W) rather than as the difference of the two
+        // star velocities, so that a large bulk velocity does not bury it in
+        // rounding (same quantity; matters in single precision at high Mach).
+        const T duRL = Ru - Lu;
+        T jL, ZL, ZR, dP, mis;
         for (;;) {
             T WL = LC * Ar<T>::sqrt_(T(1) + Lk * (P - LPt) * iPL);
             T WR = RC * Ar<T>::sqrt_(T(1) + Rk * (P - RPt) * iPR);
-            usL = Lu - (P - LPt) * Ar<T>::rcp(WL);
-            usR = Ru + (P - RPt) * Ar<T>::rcp(WR);
+            jL = (P - LPt) * Ar<T>::rcp(WL);
+            mis = duRL + (P - RPt) * Ar<T>::rcp(WR) + jL;
             ZL = T(2) * WL * WL * WL * Ar<T>::rcp(WL * WL + LC * LC);
             ZR = T(2) * WR * WR * WR * Ar<T>::rcp(WR * WR + RC * RC);
-            dP = -ZL * ZR * (usR - usL) * Ar<T>::rcp(ZL + ZR);
+            dP = -ZL * ZR * mis * Ar<T>::rcp(ZL + ZR);
             if (tabs(dP) <= tol * (P + Pd)) break;
             if (it >= a.max_iter) { conv = false; break; }
             P = tmax(P + dP, Pfloor);
             ++it;
         }
         Pst = tmax(P + dP, Pfloor);
-        ust = usL + ZR * (usR - usL) * Ar<T>::rcp(ZL + ZR);
+        ust = (Lu - jL) + ZR * mis * Ar<T>::rcp(ZL + ZR);
         if (STATS) {
             // faces -1/2 .. N-1/2 of the pencil: iteration histogram and
             // non-converged count; zone counters of R1 (after the first barrier)

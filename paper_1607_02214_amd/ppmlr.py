@@ -109,6 +109,7 @@ SIGNATURES = {
     "ppmlr_kernel_times": (C.c_int, [_P, _dp, C.POINTER(C.c_longlong)]),
     "ppmlr_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "ppmlr_get_tile": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
+    "ppmlr_autotune": (C.c_int, [_P, C.POINTER(State), C.c_int, C.POINTER(C.c_int)]),
 }
 
 _lib = None
@@ -271,6 +272,12 @@ class Context:
         v = C.c_int()
         self._chk(lib().ppmlr_get_tile(self.h, int(axis), int(dtype), C.byref(v)))
         return v.value
+
+    def autotune(self, u, reps=3, stream=None):
+        st = self._st(u, stream)
+        t = (C.c_int * 3)()
+        self._chk(lib().ppmlr_autotune(self.h, C.byref(st), int(reps), t))
+        return list(t)
 
     def last_error(self):
         m = lib().ppmlr_last_error(self.h)
