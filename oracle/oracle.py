@@ -21,17 +21,19 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ORACLE_LIB_OVERRIDE") or os.path.join(_HERE, "libppmlr_oracle.so")
 SRC_PATH = os.path.join(_HERE, "ppmlr_oracle.c")
+MLP_SRC_PATH = os.path.join(_HERE, "mlp_oracle.c")
 
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
-    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= max(
+            os.path.getmtime(SRC_PATH), os.path.getmtime(MLP_SRC_PATH)):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-           "-o", tmp, SRC_PATH, "-lm"]
+           "-o", tmp, SRC_PATH, MLP_SRC_PATH, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -109,6 +111,15 @@ def lib():
         L.oracle_riemann_alfven.argtypes = [C.c_double] * 7 + [dp, dp]
         L.oracle_dipole.argtypes = [C.POINTER(Problem), dp, dp]
         L.oracle_ghosts.restype = C.c_int
+        L.mlp_gelu.argtypes = [C.c_double]
+        L.mlp_gelu.restype = C.c_double
+        L.mlp_gelu_grad.argtypes = [C.c_double]
+        L.mlp_gelu_grad.restype = C.c_double
+        L.mlp_num_params.restype = C.c_int
+        L.mlp_forward.argtypes = [dp, C.c_int, dp, dp, dp, dp]
+        L.mlp_loss_grad.argtypes = [dp, C.c_int, dp, dp, dp]
+        L.mlp_loss_grad.restype = C.c_double
+        L.mlp_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -263,3 +274,57 @@ def riemann_alfven(rL, rR, sigma, vL, vR, bL, bR):
 
 def ghosts() -> int:
     return lib().oracle_ghosts()
+
+
+# ------------------------------------------------------------ learned guess
+
+MLP_IN, MLP_HID, MLP_OUT = 14, 64, 2
+
+
+def mlp_num_params() -> int:
+    return lib().mlp_num_params()
+
+
+def mlp_gelu(x: float) -> float:
+    return lib().mlp_gelu(float(x))
+
+
+def mlp_gelu_grad(x: float) -> float:
+    return lib().mlp_gelu_grad(float(x))
+
+
+def mlp_forward(theta, X):
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n = X.shape[0]
+    out = np.zeros((n, MLP_OUT))
+    lib().mlp_forward(_dptr(theta), n, _dptr(X), _dptr(out), None, None)
+    return out
+
+
+def mlp_loss_grad(theta, X, Y):
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    g = np.zeros(mlp_num_params())
+    loss = lib().mlp_loss_grad(_dptr(theta), X.shape[0], _dptr(X), _dptr(Y), _dptr(g))
+    return loss, g
+
+
+def mlp_adam(theta, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on theta, m, v (float64 arrays)."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    grad = np.ascontiguousarray(grad, dtype=np.float64)
+    lib().mlp_adam(_dptr(theta), _dptr(m), _dptr(v), _dptr(grad), int(t), lr, b1, b2, eps)
+
+
+def mlp_unpack(theta):
+    """Views (W1 [14,64], b1, W2 [64,64], b2, W3 [64,2], b3) into theta."""
+    o = 0
+    out = []
+    for shape in ((MLP_IN, MLP_HID), (MLP_HID,), (MLP_HID, MLP_HID), (MLP_HID,), (MLP_HID, MLP_OUT), (MLP_OUT,)):
+        n = int(np.prod(shape))
+        out.append(theta[o:o + n].reshape(shape))
+        o += n
+    return out

@@ -196,7 +196,6 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     a.nr = c->n[rax];
     a.tiles_q = (a.nq + P - 1) / P;
     a.ntiles = a.tiles_q * a.nr;
-    a.tiles_per_xcd = (a.ntiles + 7) / 8;
     const T *dummy;
     tabs(axis, a.dx, a.xc, a.xf, dummy, dummy);
     const T *t0, *t1, *t2;
@@ -226,8 +225,21 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     a.p_floor = (T)c->opt.p_floor;
     a.stats = c->opt.collect_stats ? c->d_stats : nullptr;
     a.cfl_max = c->d_cflmax;
-    a.dxw_x = c->tab[0].dxi64; a.dxw_y = c->tab[1].dxi64; a.dxw_z = c->tab[2].dxi64;
-    a.xcw_x = c->tab[0].xci64; a.xcw_y = c->tab[1].xci64; a.xcw_z = c->tab[2].xci64;
+    if (f64) {
+        a.dxw_x = (const T *)c->tab[0].dxi64; a.dxw_y = (const T *)c->tab[1].dxi64; a.dxw_z = (const T *)c->tab[2].dxi64;
+    } else {
+        a.dxw_x = (const T *)c->tab[0].dxi32; a.dxw_y = (const T *)c->tab[1].dxi32; a.dxw_z = (const T *)c->tab[2].dxi32;
+    }
+    // z sweeps (plane stride nx*ny): take the tiles covering 128 bytes along x
+    // together and step y between such groups; other sweeps keep plain order
+    if (axis == 2) {
+        int per_line = std::max(1, (int)(128 / (P * sizeof(T))));
+        a.group_q = std::min(per_line, a.tiles_q);
+    } else {
+        a.group_q = a.tiles_q;
+    }
+    a.nslots = ((a.tiles_q + a.group_q - 1) / a.group_q) * a.group_q * a.nr;
+    a.tiles_per_xcd = (a.nslots + 7) / 8;
 }
 
 template <int AX, typename T, bool STATS, bool FUSE, int SM>

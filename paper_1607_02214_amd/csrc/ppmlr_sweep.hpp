@@ -64,6 +64,8 @@ struct SweepArgs {
     long long stride_n, stride_q, stride_r;   // element strides
     int nq, nr;                 // pencils along q (memory-fastest transverse) and r
     int tiles_q, ntiles, tiles_per_xcd;
+    int group_q;                // tiles along q taken together before stepping r (>= 1)
+    int nslots;                 // enumerated tile slots: ceil(tiles_q / group_q) * group_q * nr
     const T *dx, *xc, *xf;      // sweep axis: extended widths [M], centres [M], faces [M+1]
     const T *xc_q, *xc_r;       // transverse centres (interior zones)
     const T *dx_q, *dx_r;       // transverse widths (interior zones)
@@ -80,8 +82,7 @@ struct SweepArgs {
     T tol, p_floor;
     unsigned long long *stats;  // kStatSlots x kStatWords counters or nullptr
     unsigned long long *cfl_max;// fused signal-speed max (double bits) or nullptr
-    const double *dxw_x, *dxw_y, *dxw_z;  // FP64 interior widths of all axes (fused CFL)
-    const double *xcw_x, *xcw_y, *xcw_z;  // FP64 interior centres of all axes (fused CFL)
+    const T *dxw_x, *dxw_y, *dxw_z;       // interior widths of all axes (fused CFL)
 };
 
 // Background field B_d = M [3 (m.r) r / r^5 - m / r^3] + b_ext at (x, y, z).
@@ -256,9 +257,18 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     // tiles and share L2 lines of neighbouring pencils.
     const int b = blockIdx.x;
     const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
-    if (tile >= a.ntiles) return;
-    const int tq = tile % a.tiles_q;
-    const int r = tile / a.tiles_q;
+    if (tile >= a.nslots) return;
+    // Within an XCD, groups of group_q tiles adjacent along q (sharing cache
+    // lines) run together and successive groups step along r, so that the
+    // lines in flight spread over many L2 sets when the pencil stride is a
+    // large power-of-two multiple (z sweeps).
+    const int gq = a.group_q;
+    const int gsz = gq * a.nr;
+    const int xg = tile / gsz;
+    const int rem = tile - xg * gsz;
+    const int r = rem / gq;
+    const int tq = xg * gq + (rem - r * gq);
+    if (tq >= a.tiles_q) return;
     const int q0 = tq * a.P;
 
     const int tid = threadIdx.x;
@@ -690,38 +700,48 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
 #pragma unroll
         for (int v = 0; v < 8; ++v) uo[v * a.vol] = out[v];
         if (FUSE_CFL && !masked) {
-            // signal speed of the updated zone (FP64), for the next step's dt
+            // signal speed of the updated zone, for the next step's dt (the
+            // maximum is reduced in FP64)
             int ix, iy, iz;
             if (AX == 0) { ix = g; iy = j1; iz = j2; }
             else if (AX == 1) { iy = g; iz = j1; ix = j2; }
             else { iz = g; ix = j1; iy = j2; }
-            double r_ = (double)out[0];
-            double vx = (double)out[1] / r_, vy = (double)out[2] / r_, vz = (double)out[3] / r_;
-            double px = (double)out[4], py = (double)out[5], pz = (double)out[6];
-            double p_ = ((double)gam - 1.0) * ((double)out[7] - 0.5 * r_ * (vx * vx + vy * vy + vz * vz) -
-                                                0.5 * (px * px + py * py + pz * pz));
-            if (p_ < (double)a.p_floor) p_ = (double)a.p_floor;
-            double Bx = px, By = py, Bz = pz;
+            const T r_ = out[0];
+            const T ir = Ar<T>::rcp(r_);
+            const T vx = out[1] * ir, vy = out[2] * ir, vz = out[3] * ir;
+            const T px = out[4], py = out[5], pz = out[6];
+            T p_ = (gam - T(1)) * (out[7] - T(0.5) * r_ * (vx * vx + vy * vy + vz * vz) -
+                                   T(0.5) * (px * px + py * py + pz * pz));
+            p_ = tmax(p_, a.p_floor);
+            T Bx = px, By = py, Bz = pz;
             if (a.has_bd) {
                 T bx, by, bz, x, y, z;
                 to_xyz<AX>(xci, c1, c2, x, y, z);
                 background(a, x, y, z, bx, by, bz);
-                Bx += (double)bx; By += (double)by; Bz += (double)bz;
+                Bx += bx; By += by; Bz += bz;
             }
-            double a2 = (double)gam * p_ / r_;
-            double b2 = (Bx * Bx + By * By + Bz * Bz) / r_;
-            const double ww[3] = {a.dxw_x[ix], a.dxw_y[iy], a.dxw_z[iz]};
-            const double vv[3] = {vx, vy, vz};
-            const double BB[3] = {Bx, By, Bz};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double ba2 = BB[c] * BB[c] / r_;
-                double disc = (a2 + b2) * (a2 + b2) - 4.0 * a2 * ba2;
-                disc = disc > 0.0 ? disc : 0.0;
-                double cf = __builtin_sqrt(0.5 * (a2 + b2 + __builtin_sqrt(disc)));
-                double s_ = (__builtin_fabs(vv[c]) + cf) / ww[c];
-                smax = s_ > smax ? s_ : smax;
+            const T a2 = gam * p_ * ir;
+            const T b2 = (Bx * Bx + By * By + Bz * Bz) * ir;
+            const T s2 = a2 + b2;
+            const T q4 = T(4) * a2 * ir;
+            const T wx = a.dxw_x[ix], wy = a.dxw_y[iy], wz = a.dxw_z[iz];
+            T sp = T(0);
+            {
+                T disc = tmax(s2 * s2 - q4 * Bx * Bx, T(0));
+                T cf = Ar<T>::sqrt_(T(0.5) * (s2 + Ar<T>::sqrt_(disc)));
+                sp = tmax(sp, (tabs(vx) + cf) * Ar<T>::rcp(wx));
             }
+            {
+                T disc = tmax(s2 * s2 - q4 * By * By, T(0));
+                T cf = Ar<T>::sqrt_(T(0.5) * (s2 + Ar<T>::sqrt_(disc)));
+                sp = tmax(sp, (tabs(vy) + cf) * Ar<T>::rcp(wy));
+            }
+            {
+                T disc = tmax(s2 * s2 - q4 * Bz * Bz, T(0));
+                T cf = Ar<T>::sqrt_(T(0.5) * (s2 + Ar<T>::sqrt_(disc)));
+                sp = tmax(sp, (tabs(vz) + cf) * Ar<T>::rcp(wz));
+            }
+            smax = (double)sp;
         }
     }
     if (STATS) {
