@@ -172,6 +172,34 @@ ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *penc
  * (may be NULL).  Synchronises; allocates and frees one state-sized buffer. */
 ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, int tiles[3]);
 
+/* Batched ensemble: many independent runs of different sizes, each with its
+ * own inflow and its own CFL-limited dt (the Section IV-A set-up per member),
+ * advanced together.  Advances member m (ctxs[m], states[m]) by `steps` split
+ * steps with dt computed on the device per member, exactly as ppmlr_advance
+ * would (same arithmetic, bitwise equal results for the same tiles).  Each
+ * sweep of a step is one launch that covers the tiles of every member, so
+ * the device sees one large grid instead of many small ones; per step there
+ * are four launches (per-member dt + three sweeps) whatever the member count.
+ * All states must share one dtype and stream (states[0]->stream) and all
+ * contexts the same step-counter parity; the contexts' dt, time, signal-speed
+ * and counter buffers are used as by ppmlr_advance, so none of the contexts
+ * may be in use elsewhere meanwhile.
+ * block: workgroup size 256, 512 or 1024 (every pencil + 14 ghosts must fit;
+ * 1024 is FP32 only), or 0 for the value chosen by ppmlr_ensemble_autotune
+ * (512 if it never ran); pencils per workgroup per member and axis are the
+ * most that fit the workgroup.  per_member (may be NULL) receives each
+ * member's ppmlr_status_check result.  Synchronises; allocates and frees its
+ * work tables. */
+ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
+                                double cfl, int block, ppmlr_status *per_member);
+
+/* Ensemble tile autotuner: times `reps` ensemble steps for each feasible
+ * workgroup size on library-owned copies of the states (the callers' states,
+ * step counters and times are left unchanged), stores the fastest for
+ * ensemble calls with block = 0 and returns it in *block (may be NULL). */
+ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int reps,
+                                     double cfl, int *block);
+
 #ifdef __cplusplus
 }
 #endif

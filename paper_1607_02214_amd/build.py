@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
     "--offload-arch=gfx950",
+    # multiply-adds are fused only where the source writes them in one
+    # expression, so every instantiation of the sweep (single run, ensemble,
+    # with or without counters) rounds identically
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

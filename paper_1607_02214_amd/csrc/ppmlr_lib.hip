@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -230,14 +231,10 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     } else {
         a.dxw_x = (const T *)c->tab[0].dxi32; a.dxw_y = (const T *)c->tab[1].dxi32; a.dxw_z = (const T *)c->tab[2].dxi32;
     }
-    // z sweeps (plane stride nx*ny): take the tiles covering 128 bytes along x
-    // together and step y between such groups; other sweeps keep plain order
-    if (axis == 2) {
-        int per_line = std::max(1, (int)(128 / (P * sizeof(T))));
-        a.group_q = std::min(per_line, a.tiles_q);
-    } else {
-        a.group_q = a.tiles_q;
-    }
+    // plain tile order along q then r (grouping q tiles that share cache
+    // lines before stepping r was measured on the z sweep and raised its
+    // fetched bytes, so it is left off)
+    a.group_q = a.tiles_q;
     a.nslots = ((a.tiles_q + a.group_q - 1) / a.group_q) * a.group_q * a.nr;
     a.tiles_per_xcd = (a.nslots + 7) / 8;
 }
@@ -916,6 +913,232 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
     if (t1) (void)hipEventDestroy(t1);
     (void)hipStreamSynchronize(st);
     (void)hipFree(scratch);
+    return e;
+}
+
+}  // extern "C"
+
+namespace {
+
+int g_ensemble_block = 0;   // set by ppmlr_ensemble_autotune
+
+// dt of every member from its signal-speed maximum, exactly as dt_kernel
+__global__ void ens_dt_kernel(unsigned long long *const *smax_bits, double *const *dt, double *const *t, int members,
+                              double cfl)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= members) return;
+    double smax = __longlong_as_double((long long)*smax_bits[m]);
+    double d = smax > 0.0 ? cfl / smax : 0.0;
+    *dt[m] = d;
+    *t[m] += d;
+    *smax_bits[m] = 0ull;
+}
+
+template <typename T>
+ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps, double cfl,
+                            int block)
+{
+    ppmlr_ctx *c0 = ctxs[0];
+    hipStream_t st = (hipStream_t)states[0]->stream;
+    // per axis and member: pencils per workgroup = as many as fit the block;
+    // dt from the member's device dt, signal speeds into its own slot
+    std::vector<ppmlr::SweepArgs<T>> desc((size_t)3 * n);
+    std::vector<int> mo((size_t)3 * (n + 1));
+    bool stats = false;
+    for (int ax = 0; ax < 3; ++ax) {
+        long long off = 0;
+        for (int m = 0; m < n; ++m) {
+            ppmlr_ctx *c = ctxs[m];
+            if (c->opt.collect_stats) stats = true;
+            const int M = c->n[ax] + 2 * kG;
+            const int nq = (ax == 0) ? c->n[1] : c->n[0];
+            const int P = std::max(1, std::min(block / M, nq));
+            ppmlr::SweepArgs<T> &a = desc[(size_t)ax * n + m];
+            fill_args(c, a, (T *)states[m]->u, ax, 0.0, c->d_dt, P);
+            mo[(size_t)ax * (n + 1) + m] = (int)off;
+            off += a.ntiles;
+        }
+        if (off > (long long)INT_MAX / 2) return fail(c0, PPMLR_EINVAL, "ensemble too large for one launch");
+        mo[(size_t)ax * (n + 1) + n] = (int)off;
+    }
+    std::vector<void *> allocs;
+    ppmlr_status err = PPMLR_OK;
+    auto dalloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (!err) err = hip_check(c0, hipMalloc(&p, std::max<size_t>(bytes, 16)), "hipMalloc");
+        if (p) allocs.push_back(p);
+        return p;
+    };
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (!err) err = hip_check(c0, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    };
+    auto *d_desc = (ppmlr::SweepArgs<T> *)dalloc(sizeof(ppmlr::SweepArgs<T>) * desc.size());
+    auto *d_mo = (int *)dalloc(sizeof(int) * mo.size());
+    auto *d_ptr = (void **)dalloc(sizeof(void *) * 3 * (size_t)n);
+    if (!err) {
+        std::vector<void *> ptr((size_t)3 * n);
+        for (int m = 0; m < n; ++m) {
+            ptr[m] = ctxs[m]->d_cflmax;
+            ptr[(size_t)n + m] = ctxs[m]->d_dt;
+            ptr[(size_t)2 * n + m] = ctxs[m]->d_time;
+        }
+        up(d_desc, desc.data(), sizeof(ppmlr::SweepArgs<T>) * desc.size());
+        up(d_mo, mo.data(), sizeof(int) * mo.size());
+        up(d_ptr, ptr.data(), sizeof(void *) * ptr.size());
+        // the host tables must stay alive until the copies have been made
+        if (!err) err = hip_check(c0, hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+    // signal-speed maximum of every member's current state
+    for (int m = 0; m < n && !err; ++m) err = cfl_launch(ctxs[m], states[m]);
+    const size_t lds = (size_t)(kSlotsA + kSlotsB) * block * sizeof(T);
+    static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    for (int s = 0; s < steps && !err; ++s) {
+        hipLaunchKernelGGL(ens_dt_kernel, dim3((n + 63) / 64), dim3(64), 0, st, (unsigned long long *const *)d_ptr,
+                           (double *const *)(d_ptr + n), (double *const *)(d_ptr + 2 * (size_t)n), n, cfl);
+        const int *ord = ((c0->step + s) % 2 == 0) ? even : odd;
+        for (int k = 0; k < 3 && !err; ++k) {
+            const int ax = ord[k];
+            ppmlr::EnsembleSweepArgs<T> e;
+            e.desc = d_desc + (size_t)ax * n;
+            e.mo = d_mo + (size_t)ax * (n + 1);
+            e.members = n;
+            e.total = mo[(size_t)ax * (n + 1) + n];
+            e.per_xcd = (e.total + 7) / 8;
+            const dim3 grid(8 * e.per_xcd);
+            auto launch = [&](auto kern) {
+                if (lds > 64 * 1024) {
+                    hipError_t he = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                        (int)lds);
+                    if (he != hipSuccess) { err = hip_check(c0, he, "hipFuncSetAttribute"); return; }
+                }
+                hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, e);
+            };
+#define PPMLR_ENS3(AX_, B_)                                                                              \
+            if (stats) { if (k == 2) launch(ppmlr::ensemble_sweep_kernel<AX_, T, true, true, B_>);         \
+                         else launch(ppmlr::ensemble_sweep_kernel<AX_, T, true, false, B_>); }             \
+            else { if (k == 2) launch(ppmlr::ensemble_sweep_kernel<AX_, T, false, true, B_>);              \
+                   else launch(ppmlr::ensemble_sweep_kernel<AX_, T, false, false, B_>); }
+#define PPMLR_ENS(B_)                                                                                    \
+            if (ax == 0) { PPMLR_ENS3(0, B_) } else if (ax == 1) { PPMLR_ENS3(1, B_) } else { PPMLR_ENS3(2, B_) }
+            if (block == 256) { PPMLR_ENS(256) }
+            else if (block == 512) { PPMLR_ENS(512) }
+            else {
+                if constexpr (sizeof(T) == 4) { PPMLR_ENS(1024) }
+                else err = fail(c0, PPMLR_EINVAL, "FP64 ensembles use block 256 or 512");
+            }
+#undef PPMLR_ENS
+#undef PPMLR_ENS3
+            if (!err) err = hip_check(c0, hipGetLastError(), "ensemble sweep launch");
+        }
+    }
+    // the device tables are freed once the launches that read them are done
+    (void)hipStreamSynchronize(st);
+    for (void *p : allocs) (void)hipFree(p);
+    return err;
+}
+
+ppmlr_status ensemble_check(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps, double cfl,
+                            int block)
+{
+    if (!ctxs || !states || n < 1 || steps < 0 || !(cfl > 0.0)) return PPMLR_EINVAL;
+    for (int m = 0; m < n; ++m) {
+        if (!ctxs[m] || !states[m]) return PPMLR_EINVAL;
+        ppmlr_status e = check_state(ctxs[m], states[m]);
+        if (e) return e;
+        if (states[m]->dtype != states[0]->dtype) return fail(ctxs[0], PPMLR_EINVAL, "members differ in dtype");
+        if (states[m]->stream != states[0]->stream) return fail(ctxs[0], PPMLR_EINVAL, "members differ in stream");
+        if ((ctxs[m]->step & 1) != (ctxs[0]->step & 1)) return fail(ctxs[0], PPMLR_EINVAL, "step parity differs");
+        for (int a = 0; a < 3; ++a)
+            if (ctxs[m]->n[a] + 2 * kG > block) return fail(ctxs[0], PPMLR_EINVAL, "a pencil does not fit the block");
+    }
+    if (block != 256 && block != 512 && block != 1024) return fail(ctxs[0], PPMLR_EINVAL, "block must be 256, 512 or 1024");
+    if (block == 1024 && states[0]->dtype == PPMLR_F64) return fail(ctxs[0], PPMLR_EINVAL, "FP64 block <= 512");
+    return PPMLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
+                                double cfl, int block, ppmlr_status *per_member)
+{
+    if (block == 0) block = g_ensemble_block ? g_ensemble_block : 512;
+    ppmlr_status e = ensemble_check(ctxs, states, n, steps, cfl, block);
+    if (e) return e;
+    if (steps > 0) {
+        e = states[0]->dtype == PPMLR_F64 ? ensemble_typed<double>(ctxs, states, n, steps, cfl, block)
+                                          : ensemble_typed<float>(ctxs, states, n, steps, cfl, block);
+        if (!e)
+            for (int m = 0; m < n; ++m) ctxs[m]->step += steps;
+    }
+    if (per_member)
+        for (int m = 0; m < n; ++m) per_member[m] = e ? e : ppmlr_status_check(ctxs[m], states[m]->stream);
+    return e;
+}
+
+ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int reps,
+                                     double cfl, int *block)
+{
+    if (!ctxs || !states || n < 1 || reps < 1) return PPMLR_EINVAL;
+    hipStream_t st = (hipStream_t)states[0]->stream;
+    std::vector<void *> scratch(n, nullptr);
+    std::vector<ppmlr_state> tmp(n);
+    std::vector<const ppmlr_state *> tptr(n);
+    std::vector<long long> step0(n);
+    std::vector<double> time0(n);
+    std::vector<int> stat0(n);
+    ppmlr_status e = PPMLR_OK;
+    for (int m = 0; m < n && !e; ++m) {
+        e = check_state(ctxs[m], states[m]);
+        if (e) break;
+        const size_t bytes = (size_t)8 * ctxs[m]->n[0] * ctxs[m]->n[1] * ctxs[m]->n[2] *
+                             (states[m]->dtype == PPMLR_F64 ? 8 : 4);
+        e = hip_check(ctxs[m], hipMalloc(&scratch[m], bytes), "hipMalloc");
+        if (!e) e = hip_check(ctxs[m], hipMemcpyAsync(scratch[m], states[m]->u, bytes, hipMemcpyDeviceToDevice, st),
+                              "hipMemcpyAsync");
+        tmp[m] = *states[m];
+        tmp[m].u = scratch[m];
+        tptr[m] = &tmp[m];
+        step0[m] = ctxs[m]->step;
+        stat0[m] = ctxs[m]->opt.collect_stats;
+        ctxs[m]->opt.collect_stats = 0;
+        if (!e) e = hip_check(ctxs[m], hipMemcpy(&time0[m], ctxs[m]->d_time, sizeof(double), hipMemcpyDeviceToHost),
+                              "hipMemcpy");
+    }
+    int best = 0;
+    float best_ms = 1e30f;
+    const int cands[3] = {256, 512, 1024};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (!e) e = hip_check(ctxs[0], hipEventCreate(&t0), "hipEventCreate");
+    if (!e) e = hip_check(ctxs[0], hipEventCreate(&t1), "hipEventCreate");
+    for (int ci = 0; ci < 3 && !e; ++ci) {
+        const int B = cands[ci];
+        if (ensemble_check(ctxs, tptr.data(), n, reps, cfl, B) != PPMLR_OK) continue;
+        e = hip_check(ctxs[0], hipEventRecord(t0, st), "hipEventRecord");
+        if (!e) e = ppmlr_ensemble_run(ctxs, tptr.data(), n, reps, cfl, B, nullptr);
+        if (!e) e = hip_check(ctxs[0], hipEventRecord(t1, st), "hipEventRecord");
+        if (!e) e = hip_check(ctxs[0], hipEventSynchronize(t1), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (!e) e = hip_check(ctxs[0], hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+        if (!e && ms < best_ms) { best_ms = ms; best = B; }
+        for (int m = 0; m < n; ++m) ctxs[m]->step = step0[m];
+    }
+    for (int m = 0; m < n; ++m) {
+        ctxs[m]->step = step0[m];
+        ctxs[m]->opt.collect_stats = stat0[m];
+        (void)hipMemcpy(ctxs[m]->d_time, &time0[m], sizeof(double), hipMemcpyHostToDevice);
+        if (scratch[m]) (void)hipFree(scratch[m]);
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (!e && best) {
+        g_ensemble_block = best;
+        if (block) *block = best;
+    } else if (!e) {
+        e = fail(ctxs[0], PPMLR_EINVAL, "no feasible ensemble block size");
+    }
     return e;
 }
 

@@ -240,35 +240,20 @@ __device__ inline void wave_hist(unsigned int *s_hist, bool counted, int bin)
     }
 }
 
+// One tile (P whole pencils) of a sweep, executed by one workgroup.  tq, r:
+// tile position (q tiles of P pencils, r the slow transverse index); dt: the
+// time step; cfl_max: target of the fused signal-speed maximum (FUSE_CFL);
+// stat_slot: which copy of the counters this workgroup adds to.
 // SM: LDS stride per stored value (a power of two >= P*M, so that every LDS
 // access uses an immediate offset), or 0 for a runtime stride P*M.
 template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
-__global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepArgs<T> a)
+__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, const int r, const T dt,
+                                           unsigned long long *cfl_max, const int stat_slot,
+                                           unsigned char *smem_raw, double *s_red, unsigned int *s_stat)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int S = SM > 0 ? SM : a.S;                      // LDS stride
     T *sA = reinterpret_cast<T *>(smem_raw);
     T *sB = sA + kSlotsA * S;
-    __shared__ double s_red[16];
-    __shared__ unsigned int s_stat[kStatWords];
-
-    // XCD-aware tile order: consecutive workgroups go to different XCDs
-    // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
-    // tiles and share L2 lines of neighbouring pencils.
-    const int b = blockIdx.x;
-    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
-    if (tile >= a.nslots) return;
-    // Within an XCD, groups of group_q tiles adjacent along q (sharing cache
-    // lines) run together and successive groups step along r, so that the
-    // lines in flight spread over many L2 sets when the pencil stride is a
-    // large power-of-two multiple (z sweeps).
-    const int gq = a.group_q;
-    const int gsz = gq * a.nr;
-    const int xg = tile / gsz;
-    const int rem = tile - xg * gsz;
-    const int r = rem / gq;
-    const int tq = xg * gq + (rem - r * gq);
-    if (tq >= a.tiles_q) return;
     const int q0 = tq * a.P;
 
     const int tid = threadIdx.x;
@@ -288,7 +273,6 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
         int ii = i + k;
         return (ii >= 0 && ii < M && slot_ok) ? tid + k * d : tsafe;
     };
-    const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
     const T gam = a.gamma;
 
     // transverse coordinates of the pencil
@@ -747,7 +731,7 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     if (STATS) {
         __syncthreads();
         if (tid < kStatWords && s_stat[tid] != 0u && a.stats)
-            atomicAdd(&a.stats[(b % kStatSlots) * kStatWords + tid], (unsigned long long)s_stat[tid]);
+            atomicAdd(&a.stats[stat_slot * kStatWords + tid], (unsigned long long)s_stat[tid]);
     }
     if (FUSE_CFL) {
         // wave max (all lanes active), workgroup max, one atomic per workgroup
@@ -761,9 +745,76 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
             double m = 0.0;
             const int nw = (blockDim.x + 63) >> 6;
             for (int w = 0; w < nw; ++w) m = s_red[w] > m ? s_red[w] : m;
-            atomicMax(a.cfl_max, (unsigned long long)__double_as_longlong(m));
+            atomicMax(cfl_max, (unsigned long long)__double_as_longlong(m));
         }
     }
+}
+
+// Standalone sweep: one workgroup per tile.
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
+__global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double s_red[16];
+    __shared__ unsigned int s_stat[kStatWords];
+    // XCD-aware tile order: consecutive workgroups go to different XCDs
+    // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
+    // tiles and share L2 lines of neighbouring pencils.  Within an XCD, groups
+    // of group_q tiles adjacent along q (sharing cache lines) run together and
+    // successive groups step along r, so that the lines in flight spread over
+    // many L2 sets when the pencil stride is a large power-of-two multiple
+    // (z sweeps).
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+    if (tile >= a.nslots) return;
+    const int gq = a.group_q;
+    const int gsz = gq * a.nr;
+    const int xg = tile / gsz;
+    const int rem = tile - xg * gsz;
+    const int r = rem / gq;
+    const int tq = xg * gq + (rem - r * gq);
+    if (tq >= a.tiles_q) return;
+    const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensemble sweep: one launch performs the same sweep (one axis) of
+// every member of an ensemble of independent runs (different sizes, inflows
+// and dt).  The tiles of all members are concatenated in member order
+// (mo[m] = first tile of member m, mo[members] = total) and dealt out with the
+// same XCD-aware order as the single-run kernel.  Each member's geometry, dt
+// pointer, signal-speed slot and counters are in its own descriptor, so a
+// member's arithmetic is exactly that of a single-run sweep with the same
+// tiles.  Successive sweeps are ordered by the launch boundaries: no
+// workgroup waits on another.
+template <typename T>
+struct EnsembleSweepArgs {
+    const SweepArgs<T> *desc;      // [members]: this axis's descriptor of each member
+    const int *mo;                 // [members + 1]: tile offsets
+    int members, total, per_xcd;
+};
+
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
+__global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepArgs<T> e)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double s_red[16];
+    __shared__ unsigned int s_stat[kStatWords];
+    const int b = blockIdx.x;
+    const int j = (b & 7) * e.per_xcd + (b >> 3);
+    if (j >= e.total) return;
+    int lo = 0, hi = e.members - 1;               // largest m with mo[m] <= j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (e.mo[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    const SweepArgs<T> &a = e.desc[lo];
+    const int t = j - e.mo[lo];
+    const int tq = t % a.tiles_q;
+    const int r = t / a.tiles_q;
+    const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
 }
 
 }  // namespace ppmlr

@@ -110,6 +110,10 @@ SIGNATURES = {
     "ppmlr_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "ppmlr_get_tile": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_autotune": (C.c_int, [_P, C.POINTER(State), C.c_int, C.POINTER(C.c_int)]),
+    "ppmlr_ensemble_run": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
+                                     C.c_int, C.POINTER(C.c_int)]),
+    "ppmlr_ensemble_autotune": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
+                                          C.POINTER(C.c_int)]),
 }
 
 _lib = None
@@ -293,3 +297,38 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def _ensemble_args(ctxs, states, stream):
+    n = len(ctxs)
+    if n != len(states) or n == 0:
+        raise ValueError("one state per context")
+    hs = (_P * n)(*[c.h for c in ctxs])
+    sts = [c._st(u, stream) for c, u in zip(ctxs, states)]
+    sp = (C.POINTER(State) * n)(*[C.pointer(x) for x in sts])
+    return n, hs, sts, sp
+
+
+def ensemble_run(ctxs, states, steps, cfl, block=0, stream=None):
+    """Advance every member (context, state tensor) by `steps` split steps in
+    one launch per sweep covering all members; returns the per-member status
+    codes."""
+    n, hs, sts, sp = _ensemble_args(ctxs, states, stream)
+    per = (C.c_int * n)()
+    rc = lib().ppmlr_ensemble_run(hs, sp, n, int(steps), float(cfl), int(block), per)
+    if rc != PPMLR_OK:
+        msg = lib().ppmlr_last_error(ctxs[0].h)
+        raise PPMLRError(rc, msg.decode() if msg else "")
+    return list(per)
+
+
+def ensemble_autotune(ctxs, states, reps=1, cfl=0.4, stream=None):
+    """Pick the ensemble workgroup size (256 / 512 / 1024) by timing `reps`
+    steps on copies of the states; returns it."""
+    n, hs, sts, sp = _ensemble_args(ctxs, states, stream)
+    b = C.c_int()
+    rc = lib().ppmlr_ensemble_autotune(hs, sp, n, int(reps), float(cfl), C.byref(b))
+    if rc != PPMLR_OK:
+        msg = lib().ppmlr_last_error(ctxs[0].h)
+        raise PPMLRError(rc, msg.decode() if msg else "")
+    return b.value
