@@ -75,18 +75,72 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
             zs += npen * n[axis]
         return zs, time.perf_counter() - t0
 
-    zs, el = sample(32)                      # calibration
-    rate = zs / el
-    npen = max(32, int(seconds_target * rate / (sum(n))))
-    zs, el = sample(npen)
+    sample(64)                               # warm-up (thread start-up)
+    zs = 0
+    el = 0.0
+    chunks = 0
+    while el < seconds_target:
+        z, e = sample(2048)
+        zs += z
+        el += e
+        chunks += 1
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": zs / el / 3.0,
         "unit": "zone-updates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{npen} random pencils per sweep direction of the 256x192x192 inflow-dipole start state "
-                  f"({zs} zone-sweeps, {el:.1f} s, FP64, OpenMP over pencils); zone-updates = zone-sweeps / 3",
+        "sample": f"{chunks} x 2048 random pencils per sweep direction of the 256x192x192 inflow-dipole start "
+                  f"state ({zs} zone-sweeps, {el:.1f} s, FP64, OpenMP over pencils); zone-updates = zone-sweeps / 3",
+    }
+
+
+def ensemble_leg(args):
+    """The 32-member batched ensemble (uneven cubic grids 96^3..160^3, seeded
+    solar-wind inputs), FP32, autotuned workgroup size, timed over
+    args.ensemble_steps steps after 2 warm-up steps."""
+    import torch
+    from paper_1607_02214_amd import inputs as I
+    from paper_1607_02214_amd import ppmlr
+
+    spec = I.ensemble_members(count=32, seed=4)
+    ctxs, us, zones = [], [], 0
+    for m in spec:
+        faces = I.member_faces(m["N"])
+        sw = m["sw"]
+        st = I.DipoleSetup(faces=faces, U=I.dipole_initial_state(faces, sw), inflow=sw, inner_rho=sw[0],
+                           inner_p=sw[7], p_floor=1e-8 * sw[7])
+        c = ppmlr.Context(st.faces, st.bc_lo, st.bc_hi, r_inner=st.r_inner, p_floor=st.p_floor)
+        c.set_dipole(st.moment, st.direction)
+        c.set_inflow(st.inflow)
+        c.set_inner(st.inner_rho, st.inner_p)
+        ctxs.append(c)
+        us.append(torch.from_numpy(st.U).to("cuda", torch.float32).contiguous())
+        zones += m["N"] ** 3
+    print(f"[bench] ensemble: {len(spec)} members, {zones} zones", file=sys.stderr, flush=True)
+    block = ppmlr.ensemble_autotune(ctxs, us, reps=1)
+    ppmlr.ensemble_run(ctxs, us, 2, args.cfl)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    status = ppmlr.ensemble_run(ctxs, us, args.ensemble_steps, args.cfl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    finite = all(bool(torch.isfinite(u).all().item()) for u in us)
+    times = [c.time(u) for c, u in zip(ctxs, us)]
+    return {
+        "value": zones * args.ensemble_steps / (ms / 1000.0),
+        "unit": "zone-updates/s",
+        "members": len(spec),
+        "sizes": [m["N"] for m in spec],
+        "zones": zones,
+        "steps": args.ensemble_steps,
+        "ms_per_step": ms / args.ensemble_steps,
+        "block": block,
+        "status": sorted(set(status)),
+        "finite": finite,
+        "simulated_time_range": [min(times), max(times)],
     }
 
 
@@ -99,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -217,6 +273,10 @@ def main():
                              "roofline_frac": round(ach64 / HBM_PEAK_GBS, 4), "status": status64,
                              "finite": fin64, "fp32_speedup": value / v64}
         del u64
+        torch.cuda.empty_cache()
+
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_leg(args)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
