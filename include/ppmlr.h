@@ -92,6 +92,8 @@ typedef struct {
     long long floor_hits;      /* zones whose pressure was floored */
     long long nonconverged;    /* interfaces that hit max_iter */
     long long nonphys;         /* zones with rho <= 0 or non-finite values */
+    long long guess_faces;     /* faces selected for the learned guess (learned / harvest modes) */
+    long long guess_fallbacks; /* selected faces that started from the plain guess instead */
 } ppmlr_stats_t;
 
 void ppmlr_default_options(ppmlr_options *opt);
@@ -169,7 +171,9 @@ ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *penc
 /* Tile autotuner: for each axis, times `reps` sweeps of every tile shape that
  * fits one workgroup on a library-owned copy of the state (the caller's state
  * is not modified), keeps the fastest per axis and returns them in tiles[3]
- * (may be NULL).  Synchronises; allocates and frees one state-sized buffer. */
+ * (may be NULL).  The sweeps timed use the context's initial-guess mode
+ * (the harvest mode is timed as the plain one and records nothing); they add
+ * to the counters.  Synchronises; allocates and frees one state-sized buffer. */
 ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, int tiles[3]);
 
 /* Batched ensemble: many independent runs of different sizes, each with its
@@ -199,6 +203,88 @@ ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const
  * ensemble calls with block = 0 and returns it in *block (may be NULL). */
 ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int reps,
                                      double cfl, int *block);
+
+/* ------------------------------------------------------------------ */
+/* Learned initial guess for the interface Riemann solve                 */
+/* ------------------------------------------------------------------ */
+/*
+ * The normal-pair Riemann problem at each face (Section II: the Lagrangian
+ * step solves a Riemann problem at every zone interface) is solved by a
+ * Newton iteration on the star pressure.  Its starting point is the linear
+ * (acoustic) guess, or, in the learned mode, the output of a small MLP on
+ * the faces with a strong jump.  The converged solution is the same within
+ * the iteration tolerance; only the iteration count changes.
+ *
+ * Network: 14 inputs, two hidden layers of 64 (tanh-form GELU), 2 outputs.
+ * Inputs per face: for the left then the right state,
+ *   rho/rho_m, (u - u_m)/c_m, (v_t1 - v_t1m)/c_m, (v_t2 - v_t2m)/c_m,
+ *   B_t1/sqrt(P_m), B_t2/sqrt(P_m), P/P_m,
+ * where _m are the means of the two states, c_m = sqrt(P_m/rho_m), P is the
+ * total pressure the solver sees and B_t the total transverse field.
+ * Outputs: (P* - P0)/P_m and (u* - u0)/c_m, the star pressure and velocity as
+ * residuals on the linear guess (P0, u0).  A face is selected when
+ * |P_R - P_L| > g_p min(P_L, P_R) or |u_R - u_L| > g_u c_m (default 0.1, 0.1).
+ * Parameters: PPMLR_MLP_PARAMS FP32 values, W1[14][64], b1[64], W2[64][64],
+ * b2[64], W3[64][2], b3[2], row-major with the input index first.  The
+ * kernels use BF16 weights and activations with FP32 accumulation on the
+ * matrix cores.
+ */
+#define PPMLR_GUESS_PLAIN 0
+#define PPMLR_GUESS_LEARNED 1
+#define PPMLR_GUESS_HARVEST 2
+#define PPMLR_MLP_PARAMS 5250
+#define PPMLR_RECORD_FLOATS 28
+
+/* Initial-guess mode of the FP32 sweeps of this context (FP64 sweeps always
+ * use the linear guess).  PLAIN: linear guess.  LEARNED: theta (device,
+ * PPMLR_MLP_PARAMS FP32) is copied into the context and packed into BF16 on
+ * `stream`; the call synchronises, so theta may change afterwards.
+ * HARVEST: linear guess, and every selected face appends one record to the
+ * buffer set by ppmlr_set_harvest (EINVAL if none).  Learned and harvest
+ * sweeps always count the iterations (ppmlr_stats). */
+ppmlr_status ppmlr_set_guess(ppmlr_ctx *ctx, int mode, const float *theta, void *stream);
+
+/* Face-selection thresholds g_p, g_u (>= 0) of the learned and harvest modes. */
+ppmlr_status ppmlr_set_gate(ppmlr_ctx *ctx, double rel_p, double rel_u);
+
+/* Harvest buffer (caller-owned device memory): records[capacity][28] FP32 and
+ * a device counter the sweeps increment once per offered record (the caller
+ * zeroes it; records beyond the capacity are counted, not written).  Record:
+ * [0..13] the 14 network inputs, [14..15] the 2 targets, then the solver's
+ * own scalars: P~_L, P~_R, P_d, u_L, u_R, C_L, C_R, k_L, k_R, P~0, P~*, u*
+ * (P~ = perturbation total pressure, P = P~ + P_d; C Lagrangian sound speed;
+ * k = (gamma_e + 1) / (2 gamma_e)).  records = NULL detaches the buffer (and
+ * leaves the harvest mode). */
+ppmlr_status ppmlr_set_harvest(ppmlr_ctx *ctx, float *records, long long capacity, unsigned long long *count);
+
+/* Training workspace for batches of up to max_batch samples (device buffers
+ * for packed weights and per-workgroup partial gradients). */
+typedef struct ppmlr_mlp ppmlr_mlp;
+ppmlr_status ppmlr_mlp_create(int max_batch, ppmlr_mlp **out);
+void ppmlr_mlp_destroy(ppmlr_mlp *mlp);
+const char *ppmlr_mlp_last_error(const ppmlr_mlp *mlp);
+
+/* Network outputs for n samples: X[n][ldx] (first 14 columns used) ->
+ * Y[n][ldy] (first 2 columns written).  All pointers on the device; queued on
+ * `stream`.  n = 0 does nothing (the pointers are not checked). */
+ppmlr_status ppmlr_mlp_forward(ppmlr_mlp *mlp, const float *theta, const float *X, int ldx, int n, float *Y, int ldy,
+                               void *stream);
+
+/* Loss L = (1 / 2n) sum over samples and outputs of (net - target)^2 for a
+ * batch of 1 <= n <= max_batch samples (targets Y[n][ldy], first 2 columns),
+ * and its gradient (grad: PPMLR_MLP_PARAMS FP32, theta order; may be NULL;
+ * loss: one FP32, may be NULL).  Partial sums are added in a fixed order:
+ * results are reproducible. */
+ppmlr_status ppmlr_mlp_grad(ppmlr_mlp *mlp, const float *theta, const float *X, int ldx, const float *Y, int ldy,
+                            int n, float *grad, float *loss, void *stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected, step number t >= 1) on the
+ * FP32 master parameters theta with moments m, v, using the gradient of the
+ * batch as in ppmlr_mlp_grad; loss (may be NULL) receives the batch loss
+ * before the step. */
+ppmlr_status ppmlr_mlp_train_step(ppmlr_mlp *mlp, float *theta, float *m, float *v, const float *X, int ldx,
+                                  const float *Y, int ldy, int n, int t, float lr, float beta1, float beta2,
+                                  float eps, float *loss, void *stream);
 
 #ifdef __cplusplus
 }

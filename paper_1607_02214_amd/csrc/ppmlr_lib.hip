@@ -55,6 +55,22 @@ struct ppmlr_ctx {
     struct Mark { hipEvent_t start, stop; int axis; };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> event_pool;
+    // learned Riemann guess
+    int guess = PPMLR_GUESS_PLAIN;
+    unsigned short *d_mlp_frag = nullptr;    // packed BF16 weight fragments
+    float *d_mlp_theta = nullptr;            // FP32 parameters
+    double gate_p = 0.1, gate_u = 0.1;
+    float *harvest = nullptr;                // caller-owned interface records
+    long long harvest_cap = 0;
+    unsigned long long *harvest_count = nullptr;
+};
+
+struct ppmlr_mlp {
+    int device = 0;
+    int max_batch = 0;
+    unsigned short *d_frag = nullptr;        // packed fragments of the current parameters
+    float *d_partials = nullptr;             // [max_batch / 64][kNPar + 1]
+    std::string err;
 };
 
 namespace {
@@ -237,15 +253,22 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     a.group_q = a.tiles_q;
     a.nslots = ((a.tiles_q + a.group_q - 1) / a.group_q) * a.group_q * a.nr;
     a.tiles_per_xcd = (a.nslots + 7) / 8;
+    a.mlp_frag = c->d_mlp_frag;
+    a.mlp_theta = c->d_mlp_theta;
+    a.gate_p = (T)c->gate_p;
+    a.gate_u = (T)c->gate_u;
+    a.harvest = c->harvest;
+    a.harvest_cap = c->harvest_cap;
+    a.harvest_count = c->harvest_count;
 }
 
-template <int AX, typename T, bool STATS, bool FUSE, int SM>
+template <int AX, typename T, bool STATS, bool FUSE, int SM, int GUESS = 0>
 ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
 {
     const int threads = block_threads(a.P, a.M);
     const size_t lds = (size_t)(kSlotsA + kSlotsB) * (SM > 0 ? SM : a.S) * sizeof(T);
     const int blocks = 8 * a.tiles_per_xcd;
-    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM>;
+    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM, GUESS>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute");
@@ -280,9 +303,29 @@ ppmlr_status launch_sm(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t s
     }
 }
 
+// Learned / harvest sweeps: FP32, counters on, compile-time stride.
+template <int AX, bool FUSE, int GUESS>
+ppmlr_status launch_guess(ppmlr_ctx *c, const ppmlr::SweepArgs<float> &a, hipStream_t st)
+{
+    switch (lds_stride<float>(block_threads(a.P, a.M))) {
+    case 256: return launch_one<AX, float, true, FUSE, 256, GUESS>(c, a, st);
+    case 512: return launch_one<AX, float, true, FUSE, 512, GUESS>(c, a, st);
+    case 1024: return launch_one<AX, float, true, FUSE, 1024, GUESS>(c, a, st);
+    default: return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
+    }
+}
+
 template <int AX, typename T>
 ppmlr_status launch_axis(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st, bool stats, bool fuse)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (c->guess == PPMLR_GUESS_LEARNED)
+            return fuse ? launch_guess<AX, true, ppmlr::kGuessLearned>(c, a, st)
+                        : launch_guess<AX, false, ppmlr::kGuessLearned>(c, a, st);
+        if (c->guess == PPMLR_GUESS_HARVEST)
+            return fuse ? launch_guess<AX, true, ppmlr::kGuessHarvest>(c, a, st)
+                        : launch_guess<AX, false, ppmlr::kGuessHarvest>(c, a, st);
+    }
     if (stats) return fuse ? launch_sm<AX, T, true, true>(c, a, st) : launch_sm<AX, T, true, false>(c, a, st);
     return fuse ? launch_sm<AX, T, false, true>(c, a, st) : launch_sm<AX, T, false, false>(c, a, st);
 }
@@ -620,6 +663,8 @@ void ppmlr_destroy(ppmlr_ctx *c)
         (void)hipEventDestroy(m.stop);
     }
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->d_mlp_frag) (void)hipFree(c->d_mlp_frag);
+    if (c->d_mlp_theta) (void)hipFree(c->d_mlp_theta);
     free_tables(c);
     delete c;
 }
@@ -829,6 +874,8 @@ ppmlr_status ppmlr_stats(ppmlr_ctx *c, void *stream, ppmlr_stats_t *out)
     out->floor_hits = (long long)h[32];
     out->nonconverged = (long long)h[33];
     out->nonphys = (long long)h[34];
+    out->guess_faces = (long long)h[35];
+    out->guess_fallbacks = (long long)h[36];
     return PPMLR_OK;
 }
 
@@ -881,6 +928,8 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
     if (!e) e = hip_check(c, hipEventCreate(&t1), "hipEventCreate");
     const bool prof = c->profiling;
     c->profiling = false;
+    const int guess = c->guess;             // the scratch copy is never harvested
+    if (guess == PPMLR_GUESS_HARVEST) c->guess = PPMLR_GUESS_PLAIN;
     ppmlr_state tmp = *s;
     tmp.u = scratch;
     for (int axis = 0; axis < 3 && !e; ++axis) {
@@ -909,6 +958,7 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
         if (tiles) tiles[axis] = best;
     }
     c->profiling = prof;
+    c->guess = guess;
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     (void)hipStreamSynchronize(st);
@@ -1147,6 +1197,168 @@ ppmlr_status ppmlr_get_tile(const ppmlr_ctx *c, int axis, int dtype, int *pencil
     if (!c || axis < 0 || axis > 2 || !pencils) return PPMLR_EINVAL;
     *pencils = pick_tile(c, axis, dtype == PPMLR_F64 ? 8 : 4);
     return PPMLR_OK;
+}
+
+
+// ---------------------------------------------------------------- learned guess
+
+ppmlr_status ppmlr_set_guess(ppmlr_ctx *c, int mode, const float *theta, void *stream)
+{
+    if (!c) return PPMLR_EINVAL;
+    if (mode != PPMLR_GUESS_PLAIN && mode != PPMLR_GUESS_LEARNED && mode != PPMLR_GUESS_HARVEST)
+        return fail(c, PPMLR_EINVAL, "unknown guess mode");
+    if (mode == PPMLR_GUESS_LEARNED) {
+        if (!theta) return fail(c, PPMLR_EINVAL, "the learned guess needs parameters");
+        hipStream_t st = (hipStream_t)stream;
+        ppmlr_status e = PPMLR_OK;
+        if (!c->d_mlp_frag)
+            e = hip_check(c, hipMalloc((void **)&c->d_mlp_frag, sizeof(unsigned short) * 256 * ppmlr::mlp::kTiles),
+                          "hipMalloc");
+        if (!e && !c->d_mlp_theta)
+            e = hip_check(c, hipMalloc((void **)&c->d_mlp_theta, sizeof(float) * ppmlr::mlp::kNPar), "hipMalloc");
+        if (!e) e = hip_check(c, hipMemcpyAsync(c->d_mlp_theta, theta, sizeof(float) * ppmlr::mlp::kNPar,
+                                                hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        if (e) return e;
+        const int n = 256 * ppmlr::mlp::kTiles;
+        hipLaunchKernelGGL(ppmlr::mlp::pack_kernel, dim3((n + 255) / 256), dim3(256), 0, st, c->d_mlp_theta,
+                           c->d_mlp_frag, ppmlr::mlp::kTiles);
+        e = hip_check(c, hipGetLastError(), "pack launch");
+        if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (e) return e;
+    }
+    if (mode == PPMLR_GUESS_HARVEST && !c->harvest) return fail(c, PPMLR_EINVAL, "no harvest buffer set");
+    c->guess = mode;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_gate(ppmlr_ctx *c, double rel_p, double rel_u)
+{
+    if (!c) return PPMLR_EINVAL;
+    if (!(rel_p >= 0.0) || !(rel_u >= 0.0)) return fail(c, PPMLR_EINVAL, "gate thresholds must be >= 0");
+    c->gate_p = rel_p;
+    c->gate_u = rel_u;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_harvest(ppmlr_ctx *c, float *records, long long capacity, unsigned long long *count)
+{
+    if (!c) return PPMLR_EINVAL;
+    if (records && (capacity < 0 || !count)) return fail(c, PPMLR_EINVAL, "harvest buffer needs a capacity and a counter");
+    c->harvest = records;
+    c->harvest_cap = records ? capacity : 0;
+    c->harvest_count = records ? count : nullptr;
+    if (!records && c->guess == PPMLR_GUESS_HARVEST) c->guess = PPMLR_GUESS_PLAIN;
+    return PPMLR_OK;
+}
+
+// ---------------------------------------------------------------- MLP workspace
+
+static ppmlr_status mlp_fail(ppmlr_mlp *w, ppmlr_status s, const std::string &msg)
+{
+    if (w) w->err = msg;
+    return s;
+}
+
+static ppmlr_status mlp_check(ppmlr_mlp *w, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return PPMLR_OK;
+    return mlp_fail(w, e == hipErrorOutOfMemory ? PPMLR_ENOMEM : PPMLR_EDEVICE,
+                    std::string(what) + ": " + hipGetErrorString(e));
+}
+
+ppmlr_status ppmlr_mlp_create(int max_batch, ppmlr_mlp **out)
+{
+    if (!out || max_batch < 1) return PPMLR_EINVAL;
+    *out = nullptr;
+    ppmlr_mlp *w = new ppmlr_mlp();
+    w->max_batch = max_batch;
+    ppmlr_status e = mlp_check(w, hipGetDevice(&w->device), "hipGetDevice");
+    const size_t blocks = (size_t)(max_batch + 63) / 64;
+    if (!e) e = mlp_check(w, hipMalloc((void **)&w->d_frag, sizeof(unsigned short) * 256 * ppmlr::mlp::kTiles), "hipMalloc");
+    if (!e) e = mlp_check(w, hipMalloc((void **)&w->d_partials, sizeof(float) * blocks * (ppmlr::mlp::kNPar + 1)),
+                          "hipMalloc");
+    if (e) {
+        ppmlr_mlp_destroy(w);
+        return e;
+    }
+    *out = w;
+    return PPMLR_OK;
+}
+
+void ppmlr_mlp_destroy(ppmlr_mlp *w)
+{
+    if (!w) return;
+    (void)hipDeviceSynchronize();
+    if (w->d_frag) (void)hipFree(w->d_frag);
+    if (w->d_partials) (void)hipFree(w->d_partials);
+    delete w;
+}
+
+const char *ppmlr_mlp_last_error(const ppmlr_mlp *w) { return w ? w->err.c_str() : "null workspace"; }
+
+static ppmlr_status mlp_pack(ppmlr_mlp *w, const float *theta, hipStream_t st)
+{
+    const int n = 256 * ppmlr::mlp::kTiles;
+    hipLaunchKernelGGL(ppmlr::mlp::pack_kernel, dim3((n + 255) / 256), dim3(256), 0, st, theta, w->d_frag,
+                       ppmlr::mlp::kTiles);
+    return mlp_check(w, hipGetLastError(), "pack launch");
+}
+
+ppmlr_status ppmlr_mlp_forward(ppmlr_mlp *w, const float *theta, const float *X, int ldx, int n, float *Y, int ldy,
+                               void *stream)
+{
+    if (!w) return PPMLR_EINVAL;
+    if (n < 0) return mlp_fail(w, PPMLR_EINVAL, "negative sample count");
+    if (n == 0) return PPMLR_OK;
+    if (!theta || !X || !Y || ldx < ppmlr::mlp::kIn || ldy < ppmlr::mlp::kOut)
+        return mlp_fail(w, PPMLR_EINVAL, "bad forward arguments");
+    hipStream_t st = (hipStream_t)stream;
+    ppmlr_status e = mlp_pack(w, theta, st);
+    if (e) return e;
+    hipLaunchKernelGGL(ppmlr::mlp::forward_kernel, dim3((n + 63) / 64), dim3(64), 0, st, X, ldx, n,
+                       (const unsigned short *)w->d_frag, theta, Y, ldy);
+    return mlp_check(w, hipGetLastError(), "forward launch");
+}
+
+static ppmlr_status mlp_grad_launch(ppmlr_mlp *w, const float *theta, const float *X, int ldx, const float *Y,
+                                    int ldy, int n, hipStream_t st)
+{
+    if (!theta || !X || !Y || n < 1 || n > w->max_batch || ldx < ppmlr::mlp::kIn || ldy < ppmlr::mlp::kOut)
+        return mlp_fail(w, PPMLR_EINVAL, "bad batch arguments (1 <= n <= max_batch)");
+    ppmlr_status e = mlp_pack(w, theta, st);
+    if (e) return e;
+    hipLaunchKernelGGL(ppmlr::mlp::grad_kernel, dim3((n + 63) / 64), dim3(64), 0, st, X, ldx, Y, ldy, n,
+                       (const unsigned short *)w->d_frag, theta, w->d_partials);
+    return mlp_check(w, hipGetLastError(), "grad launch");
+}
+
+ppmlr_status ppmlr_mlp_grad(ppmlr_mlp *w, const float *theta, const float *X, int ldx, const float *Y, int ldy, int n,
+                            float *grad, float *loss, void *stream)
+{
+    if (!w) return PPMLR_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    ppmlr_status e = mlp_grad_launch(w, theta, X, ldx, Y, ldy, n, st);
+    if (e) return e;
+    const int np = ppmlr::mlp::kNPar + 1;
+    hipLaunchKernelGGL(ppmlr::mlp::reduce_adam_kernel, dim3((np + 255) / 256), dim3(256), 0, st, w->d_partials,
+                       (n + 63) / 64, grad, loss, (float *)nullptr, (float *)nullptr, (float *)nullptr, 0, 0, 0.0f,
+                       0.0f, 0.0f, 0.0f);
+    return mlp_check(w, hipGetLastError(), "reduce launch");
+}
+
+ppmlr_status ppmlr_mlp_train_step(ppmlr_mlp *w, float *theta, float *m, float *v, const float *X, int ldx,
+                                  const float *Y, int ldy, int n, int t, float lr, float beta1, float beta2,
+                                  float eps, float *loss, void *stream)
+{
+    if (!w) return PPMLR_EINVAL;
+    if (!m || !v || t < 1) return mlp_fail(w, PPMLR_EINVAL, "Adam needs moments and a step number >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    ppmlr_status e = mlp_grad_launch(w, theta, X, ldx, Y, ldy, n, st);
+    if (e) return e;
+    const int np = ppmlr::mlp::kNPar + 1;
+    hipLaunchKernelGGL(ppmlr::mlp::reduce_adam_kernel, dim3((np + 255) / 256), dim3(256), 0, st, w->d_partials,
+                       (n + 63) / 64, (float *)nullptr, loss, theta, m, v, 1, t, lr, beta1, beta2, eps);
+    return mlp_check(w, hipGetLastError(), "adam launch");
 }
 
 }  // extern "C"

@@ -20,6 +20,7 @@
 // The pencil axis is a template parameter so that all component indexing is
 // static (no private arrays with dynamic indices).
 #pragma once
+#include "ppmlr_mlp.hpp"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,7 +29,8 @@ namespace ppmlr {
 constexpr int kG = 7;           // ghost zones per side
 constexpr int kSlotsA = 14;     // values per zone in LDS buffer A
 constexpr int kSlotsB = 8;      // values per zone in LDS buffer B
-constexpr int kStatWords = 35;  // iteration histogram [32], floors, nonconverged, nonphys
+constexpr int kStatWords = 37;  // iteration histogram [32], floors, nonconverged, nonphys,
+                                // learned-guess faces, learned-guess fallbacks
 constexpr int kStatSlots = 64;  // copies of the counters (workgroup b adds to copy b % 64)
 
 enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
@@ -83,7 +85,17 @@ struct SweepArgs {
     unsigned long long *stats;  // kStatSlots x kStatWords counters or nullptr
     unsigned long long *cfl_max;// fused signal-speed max (double bits) or nullptr
     const T *dxw_x, *dxw_y, *dxw_z;       // interior widths of all axes (fused CFL)
+    // learned Riemann guess (FP32 single-run sweeps)
+    const unsigned short *mlp_frag;       // packed BF16 weight fragments
+    const float *mlp_theta;               // FP32 parameters (biases)
+    T gate_p, gate_u;                     // relative pressure / velocity jump that selects a face
+    float *harvest;                       // [harvest_cap][28] interface records or nullptr
+    long long harvest_cap;
+    unsigned long long *harvest_count;    // records offered (may exceed the capacity)
 };
+
+// Riemann initial-guess modes of the sweep body
+enum { kGuessPlain = 0, kGuessLearned = 1, kGuessHarvest = 2 };
 
 // Background field B_d = M [3 (m.r) r / r^5 - m / r^3] + b_ext at (x, y, z).
 template <typename T>
@@ -246,11 +258,18 @@ __device__ inline void wave_hist(unsigned int *s_hist, bool counted, int bin)
 // stat_slot: which copy of the counters this workgroup adds to.
 // SM: LDS stride per stored value (a power of two >= P*M, so that every LDS
 // access uses an immediate offset), or 0 for a runtime stride P*M.
-template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
+// GUESS: initial guess of the normal-pair Newton iteration: the plain linear
+// guess, the learned (MLP) guess on selected faces, or the plain guess with
+// the selected faces' states and solutions recorded for training.  s_guess:
+// one LDS counter (learned mode).
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, const int r, const T dt,
                                            unsigned long long *cfl_max, const int stat_slot,
-                                           unsigned char *smem_raw, double *s_red, unsigned int *s_stat)
+                                           unsigned char *smem_raw, double *s_red, unsigned int *s_stat,
+                                           unsigned int *s_guess = nullptr)
 {
+    static_assert(GUESS == kGuessPlain || (SM > 0 && sizeof(T) == 4 && STATS),
+                  "learned / harvest modes are FP32 sweeps with a compile-time stride and counters");
     const int S = SM > 0 ? SM : a.S;                      // LDS stride
     T *sA = reinterpret_cast<T *>(smem_raw);
     T *sB = sA + kSlotsA * S;
@@ -258,6 +277,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
 
     const int tid = threadIdx.x;
     if (STATS && tid < kStatWords) s_stat[tid] = 0u;   // ordered by the first barrier
+    if (GUESS == kGuessLearned && tid == 0) s_guess[0] = 0u;
     const int Suse = a.S, M = a.M, N = a.N, P = a.P;
     const bool slot_ok = tid < Suse;
     int p, i;
@@ -444,6 +464,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     // left face (i-1/2); normal pair traced with y_n, Alfven pair with y_A
     // right-face (L) state, kept in registers
     T LPt, Lu, LC, Lk, Lr, Lv1, Lv2, Lb1, Lb2;
+    T LrN, LT1, LT2;      // normal-pair density and total transverse field (guess features)
     {
         T r_ = avgR(pLc[0], pDc[0], p6c[0], yn);
         T u_ = avgR(pLc[1], pDc[1], p6c[1], yn);
@@ -458,6 +479,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         if (Pt_ + Pd < T(0.5) * P0) Pt_ = T(0.5) * P0 - Pd;
         T ge = C * C * Ar<T>::rcp(r_ * (Pt_ + Pd));
         LPt = Pt_;
+        LrN = r_;
+        LT1 = T1;
+        LT2 = T2;
         Lu = u_ + corrU;
         LC = C;
         Lk = (ge + T(1)) * Ar<T>::rcp(T(2) * ge);
@@ -491,6 +515,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             sA[6 * S + tid] = avgL(pLc[3], pDc[3], p6c[3], yA) + corrV2;
             sA[7 * S + tid] = avgL(pLc[4], pDc[4], p6c[4], yA) + corrB1;
             sA[8 * S + tid] = avgL(pLc[5], pDc[5], p6c[5], yA) + corrB2;
+            if (GUESS != kGuessPlain) {
+                sA[9 * S + tid] = r_;
+                sA[10 * S + tid] = T1;
+                sA[11 * S + tid] = T2;
+            }
         }
     }
     __syncthreads();
@@ -501,6 +530,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     T RPt = sA[0 * S + sp1], Ru = sA[1 * S + sp1], RC = sA[2 * S + sp1], Rk = sA[3 * S + sp1];
     T Rr = sA[4 * S + sp1], Rv1 = sA[5 * S + sp1], Rv2 = sA[6 * S + sp1];
     T Rb1 = sA[7 * S + sp1], Rb2 = sA[8 * S + sp1];
+    T RrN = LrN, RT1 = LT1, RT2 = LT2;
+    if (GUESS != kGuessPlain && face_ok) {
+        RrN = sA[9 * S + sp1];
+        RT1 = sA[10 * S + sp1];
+        RT2 = sA[11 * S + sp1];
+    }
     if (!face_ok) {  // keep unused lanes trivial (no Newton iterations)
         RPt = LPt; Ru = Lu; RC = LC; Rk = Lk; Rr = Lr; Rv1 = Lv1; Rv2 = Lv2; Rb1 = Lb1; Rb2 = Lb2;
     }
@@ -513,6 +548,69 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         const T tol = a.tol;
         T P = LPt + LC * ((RPt - LPt) + RC * (Lu - Ru)) * Ar<T>::rcp(LC + RC);
         P = tmax(P, Pfloor);
+        const T P0 = P;
+        // Faces with a strong jump are selected for the learned guess.  Its
+        // 14 inputs: both sides' (rho, u, v_t1, v_t2, B_t1, B_t2, P) of the
+        // normal-pair problem, normalised by the pair means (velocities
+        // relative to the mean, scaled by c = sqrt(P/rho); fields by
+        // sqrt(P)).  Outputs: (P* - P0) / P and (u* - u0) / c.
+        bool gate = false;
+        T feat[14], Pbar = T(1), cbar = T(1);
+        if (GUESS != kGuessPlain) {
+            const T rbar = T(0.5) * (LrN + RrN);
+            Pbar = T(0.5) * (PL + PR);
+            const T irb = Ar<T>::rcp(rbar), iPb = Ar<T>::rcp(Pbar);
+            cbar = Ar<T>::sqrt_(Pbar * irb);
+            const T icb = Ar<T>::rcp(cbar), ibs = Ar<T>::rsqrt(Pbar);
+            const T ub = T(0.5) * (Lu + Ru), v1b = T(0.5) * (Lv1 + Rv1), v2b = T(0.5) * (Lv2 + Rv2);
+            gate = face_ok && (tabs(PR - PL) > a.gate_p * tmin(PL, PR) || tabs(Ru - Lu) > a.gate_u * cbar);
+            feat[0] = LrN * irb; feat[1] = (Lu - ub) * icb; feat[2] = (Lv1 - v1b) * icb; feat[3] = (Lv2 - v2b) * icb;
+            feat[4] = LT1 * ibs; feat[5] = LT2 * ibs; feat[6] = PL * iPb;
+            feat[7] = RrN * irb; feat[8] = (Ru - ub) * icb; feat[9] = (Rv1 - v1b) * icb; feat[10] = (Rv2 - v2b) * icb;
+            feat[11] = RT1 * ibs; feat[12] = RT2 * ibs; feat[13] = PR * iPb;
+            if (STATS) wave_add(&s_stat[35], gate);
+        }
+        if constexpr (GUESS == kGuessLearned) {
+            // Compact the selected faces of the workgroup into buffer B
+            // (free until the fluxes are written), run the network on them
+            // 64 at a time on the matrix cores, and start Newton from its
+            // pressure where that is finite and above the floor.
+            constexpr int kCap = ((8 * SM * (int)sizeof(T)) / 40) / 64 * 64;
+            const int lane = tid & 63;
+            const unsigned long long bal = __ballot(gate);
+            int base = 0;
+            if (lane == 0 && bal) base = (int)atomicAdd(&s_guess[0], (unsigned int)__popcll(bal));
+            base = __shfl(base, 0);
+            const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+            unsigned short *F = reinterpret_cast<unsigned short *>(sB);
+            float *Yo = reinterpret_cast<float *>(F + kCap * 16);
+            if (gate && slot < kCap) {
+                unsigned int w[8];
+#pragma unroll
+                for (int k = 0; k < 7; ++k)
+                    w[k] = (unsigned int)mlp::f2bf((float)feat[2 * k]) |
+                           ((unsigned int)mlp::f2bf((float)feat[2 * k + 1]) << 16);
+                w[7] = 0u;
+                uint4 *dst = reinterpret_cast<uint4 *>(F + slot * 16);
+                dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+                dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+            }
+            __syncthreads();
+            const int nf = min((int)s_guess[0], kCap);
+            for (int b0 = (tid >> 6) * 64; b0 < nf; b0 += (int)(blockDim.x >> 6) * 64)
+                mlp::forward_wave(F + b0 * 16, a.mlp_frag, a.mlp_theta, Yo + b0 * 2, 2);
+            __syncthreads();
+            bool used = false;
+            if (gate && slot < kCap) {
+                const T Pg = P + Pbar * (T)Yo[slot * 2];
+                if (__builtin_isfinite(Pg) && Pg > Pfloor) {
+                    P = Pg;
+                    used = true;
+                }
+            }
+            if (STATS) wave_add(&s_stat[36], gate && !used);
+            __syncthreads();   // buffer B is written with the fluxes next
+        }
         int it = 0;
         bool conv = true;
         // The velocity mismatch u*_R - u*_L is formed from differences
@@ -536,6 +634,31 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         }
         Pst = tmax(P + dP, Pfloor);
         ust = (Lu - jL) + ZR * mis * Ar<T>::rcp(ZL + ZR);
+        if constexpr (GUESS == kGuessHarvest) {
+            // record the selected faces: inputs, targets and the solver's own
+            // scalars (for checks against an independent solver)
+            const int lane = tid & 63;
+            const unsigned long long bal = __ballot(gate);
+            if (bal && a.harvest) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(a.harvest_count, (unsigned long long)__popcll(bal));
+                base = __shfl(base, 0);
+                const unsigned long long slot = base + (unsigned long long)__popcll(bal & ((1ull << lane) - 1ull));
+                if (gate && slot < (unsigned long long)a.harvest_cap) {
+                    float *rec = a.harvest + slot * mlp::kRecord;
+                    const T u0 = (LC * Lu + RC * Ru - (RPt - LPt)) * Ar<T>::rcp(LC + RC);
+#pragma unroll
+                    for (int k = 0; k < 14; ++k) rec[k] = (float)feat[k];
+                    rec[14] = (float)((Pst - P0) * Ar<T>::rcp(Pbar));
+                    rec[15] = (float)((ust - u0) * Ar<T>::rcp(cbar));
+                    rec[16] = (float)LPt; rec[17] = (float)RPt; rec[18] = (float)Pd;
+                    rec[19] = (float)Lu;  rec[20] = (float)Ru;
+                    rec[21] = (float)LC;  rec[22] = (float)RC;
+                    rec[23] = (float)Lk;  rec[24] = (float)Rk;
+                    rec[25] = (float)P0;  rec[26] = (float)Pst; rec[27] = (float)ust;
+                }
+            }
+        }
         if (STATS) {
             // faces -1/2 .. N-1/2 of the pencil: iteration histogram and
             // non-converged count; zone counters of R1 (after the first barrier)
@@ -751,12 +874,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
 }
 
 // Standalone sweep: one workgroup per tile.
-template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain>
 __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_red[16];
     __shared__ unsigned int s_stat[kStatWords];
+    __shared__ unsigned int s_guess[1];
     // XCD-aware tile order: consecutive workgroups go to different XCDs
     // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
     // tiles and share L2 lines of neighbouring pencils.  Within an XCD, groups
@@ -775,7 +899,8 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     const int tq = xg * gq + (rem - r * gq);
     if (tq >= a.tiles_q) return;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat,
+                                                  s_guess);
 }
 
 // ---------------------------------------------------------------------------

@@ -325,3 +325,38 @@ def blast_state(faces, seed=0, gamma=GAMMA, B0vec=(0.5, 0.3, -0.2)):
     rho = np.where(inside, 2.0, 1.0)
     z0 = 0 * X
     return conserved(rho, z0, z0, z0, B0vec[0] + z0, B0vec[1] + z0, B0vec[2] + z0, p, gamma)
+
+
+# ---------------------------------------------------------------------------
+# Learned Riemann guess: initial parameters and synthetic samples
+
+MLP_SHAPES = ((14, 64), (64,), (64, 64), (64,), (64, 2), (2,))
+
+
+def mlp_init(seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    """Initial parameters of the 14-64-64-2 network as one FP32 vector
+    (W1, b1, W2, b2, W3, b3, row-major, input index first): weights drawn
+    uniformly on +-scale*sqrt(6 / (fan_in + fan_out)) (Glorot & Bengio 2010),
+    biases zero.  PCG64(seed)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            lim = scale * np.sqrt(6.0 / (shape[0] + shape[1]))
+            parts.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_samples(n: int, seed: int = 0, spread: float = 1.0):
+    """n synthetic network inputs of the guess's feature ranges: densities and
+    pressures near 1 (ratios up to e^spread), velocities and fields O(spread)."""
+    rng = np.random.default_rng(seed)
+    X = np.empty((n, 14), dtype=np.float32)
+    for base in (0, 7):
+        X[:, base + 0] = np.exp(rng.uniform(-spread, spread, n))
+        X[:, base + 1:base + 4] = rng.normal(0.0, 0.5 * spread, (n, 3))
+        X[:, base + 4:base + 6] = rng.normal(0.0, 0.5 * spread, (n, 2))
+        X[:, base + 6] = np.exp(rng.uniform(-spread, spread, n))
+    return X

@@ -28,6 +28,9 @@ PPMLR_ENOMEM = -6
 PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
 F32, F64 = 0, 1
 GHOSTS = 7
+GUESS_PLAIN, GUESS_LEARNED, GUESS_HARVEST = 0, 1, 2
+MLP_PARAMS = 5250
+RECORD_FLOATS = 28
 
 _STATUS_NAMES = {0: "PPMLR_OK", -1: "PPMLR_EINVAL", -2: "PPMLR_ECFL", -3: "PPMLR_ERIEMANN",
                  -4: "PPMLR_ENONPHYS", -5: "PPMLR_EDEVICE", -6: "PPMLR_ENOMEM"}
@@ -75,11 +78,14 @@ class Stats(C.Structure):
         ("floor_hits", C.c_longlong),
         ("nonconverged", C.c_longlong),
         ("nonphys", C.c_longlong),
+        ("guess_faces", C.c_longlong),
+        ("guess_fallbacks", C.c_longlong),
     ]
 
     def as_dict(self):
         return {"iters_hist": list(self.iters_hist), "floor_hits": self.floor_hits,
-                "nonconverged": self.nonconverged, "nonphys": self.nonphys}
+                "nonconverged": self.nonconverged, "nonphys": self.nonphys,
+                "guess_faces": self.guess_faces, "guess_fallbacks": self.guess_fallbacks}
 
 
 # exported symbols and their signatures (mirrors include/ppmlr.h)
@@ -114,6 +120,16 @@ SIGNATURES = {
                                      C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_ensemble_autotune": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
                                           C.POINTER(C.c_int)]),
+    "ppmlr_set_guess": (C.c_int, [_P, C.c_int, _P, _P]),
+    "ppmlr_set_gate": (C.c_int, [_P, C.c_double, C.c_double]),
+    "ppmlr_set_harvest": (C.c_int, [_P, _P, C.c_longlong, _P]),
+    "ppmlr_mlp_create": (C.c_int, [C.c_int, C.POINTER(_P)]),
+    "ppmlr_mlp_destroy": (None, [_P]),
+    "ppmlr_mlp_last_error": (C.c_char_p, [_P]),
+    "ppmlr_mlp_forward": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P, C.c_int, _P]),
+    "ppmlr_mlp_grad": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, _P, _P, _P]),
+    "ppmlr_mlp_train_step": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, C.c_float,
+                                       C.c_float, C.c_float, C.c_float, _P, _P]),
 }
 
 _lib = None
@@ -283,6 +299,32 @@ class Context:
         self._chk(lib().ppmlr_autotune(self.h, C.byref(st), int(reps), t))
         return list(t)
 
+    def set_guess(self, mode, theta=None, stream=None):
+        """mode: GUESS_PLAIN, GUESS_LEARNED (theta: device float32 tensor of
+        MLP_PARAMS values) or GUESS_HARVEST."""
+        ptr = None
+        if theta is not None:
+            _check_f32(theta, (MLP_PARAMS,))
+            ptr = C.c_void_p(theta.data_ptr())
+        return self._chk(lib().ppmlr_set_guess(self.h, int(mode), ptr, _stream(theta, stream)))
+
+    def set_gate(self, rel_p, rel_u):
+        return self._chk(lib().ppmlr_set_gate(self.h, float(rel_p), float(rel_u)))
+
+    def set_harvest(self, records=None, count=None):
+        """records: device float32 tensor [capacity, RECORD_FLOATS]; count: device
+        int64 tensor of one element (zeroed by the caller).  None detaches."""
+        if records is None:
+            return self._chk(lib().ppmlr_set_harvest(self.h, None, 0, None))
+        import torch
+        if records.dtype != torch.float32 or not records.is_cuda or not records.is_contiguous() \
+                or records.dim() != 2 or records.shape[1] != RECORD_FLOATS:
+            raise ValueError("records must be a contiguous device float32 tensor [capacity, 28]")
+        if count is None or count.dtype != torch.int64 or not count.is_cuda or count.numel() != 1:
+            raise ValueError("count must be a device int64 tensor of one element")
+        return self._chk(lib().ppmlr_set_harvest(self.h, C.c_void_p(records.data_ptr()), int(records.shape[0]),
+                                                 C.c_void_p(count.data_ptr())))
+
     def last_error(self):
         m = lib().ppmlr_last_error(self.h)
         return m.decode() if m else ""
@@ -332,3 +374,92 @@ def ensemble_autotune(ctxs, states, reps=1, cfl=0.4, stream=None):
         msg = lib().ppmlr_last_error(ctxs[0].h)
         raise PPMLRError(rc, msg.decode() if msg else "")
     return b.value
+
+
+def _stream(t, stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    dev = t.device if t is not None else torch.device("cuda")
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check_f32(t, shape=None, ld=None):
+    """Device float32 tensor: a contiguous vector of the given shape, or (ld)
+    a row-major matrix with at least ld columns (row stride free)."""
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise ValueError("expected a device float32 tensor")
+    if shape is not None and (tuple(t.shape) != tuple(shape) or not t.is_contiguous()):
+        raise ValueError(f"expected a contiguous tensor of shape {shape}, got {tuple(t.shape)}")
+    if ld is not None and (t.dim() != 2 or t.shape[1] < ld or t.stride(1) != 1):
+        raise ValueError(f"expected a row-major 2-D tensor with at least {ld} columns")
+
+
+class MLP:
+    """Training workspace of the learned Riemann guess (ppmlr_mlp)."""
+
+    def __init__(self, max_batch):
+        h = _P()
+        rc = lib().ppmlr_mlp_create(int(max_batch), C.byref(h))
+        if rc != PPMLR_OK:
+            raise PPMLRError(rc, "ppmlr_mlp_create failed")
+        self.h = h
+        self.max_batch = int(max_batch)
+
+    def _chk(self, rc):
+        if rc != PPMLR_OK:
+            msg = lib().ppmlr_mlp_last_error(self.h)
+            raise PPMLRError(rc, msg.decode() if msg else "")
+        return rc
+
+    def forward(self, theta, X, out=None, stream=None):
+        """X: [n, >=14] device float32 -> [n, 2]."""
+        import torch
+        _check_f32(theta, (MLP_PARAMS,))
+        _check_f32(X, ld=14)
+        n = X.shape[0]
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+        _check_f32(out, ld=2)
+        self._chk(lib().ppmlr_mlp_forward(self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(X.data_ptr()),
+                                          int(X.stride(0)), int(n), C.c_void_p(out.data_ptr()), int(out.stride(0)),
+                                          _stream(X, stream)))
+        return out
+
+    def grad(self, theta, X, Y, stream=None):
+        """Returns (gradient [MLP_PARAMS], loss [1]) device tensors."""
+        import torch
+        _check_f32(theta, (MLP_PARAMS,))
+        _check_f32(X, ld=14)
+        _check_f32(Y, ld=2)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        self._chk(lib().ppmlr_mlp_grad(self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(X.data_ptr()),
+                                       int(X.stride(0)), C.c_void_p(Y.data_ptr()), int(Y.stride(0)), int(X.shape[0]),
+                                       C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr()), _stream(X, stream)))
+        return g, loss
+
+    def train_step(self, theta, m, v, X, Y, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, stream=None):
+        """One Adam step in place on theta, m, v (device float32); loss: optional
+        device float32 tensor of one element receiving the batch loss."""
+        for a in (theta, m, v):
+            _check_f32(a, (MLP_PARAMS,))
+        _check_f32(X, ld=14)
+        _check_f32(Y, ld=2)
+        lp = C.c_void_p(loss.data_ptr()) if loss is not None else None
+        return self._chk(lib().ppmlr_mlp_train_step(
+            self.h, C.c_void_p(theta.data_ptr()), C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()),
+            C.c_void_p(X.data_ptr()), int(X.stride(0)), C.c_void_p(Y.data_ptr()), int(Y.stride(0)), int(X.shape[0]),
+            int(t), float(lr), float(beta1), float(beta2), float(eps), lp, _stream(X, stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ppmlr_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
