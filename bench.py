@@ -27,6 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (packed); 78.6 without packed FP32 instructions
+FP32_UNPACKED_TFLOPS = 78.6
+# FP32 operations per zone-sweep: adds + multiplies + transcendentals + 2 x
+# fused multiply-adds per lane, from the SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F32
+# counters of the sweep kernels on this workload (x 1513, y 1445, z 1468;
+# the smallest is used)
+FLOPS_PER_ZONE_SWEEP = 1445.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -95,6 +102,80 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
     }
 
 
+def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
+    """The learned Riemann guess on the same workload: harvest interface
+    records from a plain FP32 run of the start state, train the network on
+    them with the GPU kernels, then time the learned-guess run over the same
+    warm-up + timed steps as the plain run and compare the final states."""
+    import numpy as np
+    import torch
+    from paper_1607_02214_amd import learned, ppmlr
+
+    t0 = time.perf_counter()
+    ctx_h = make_ctx()
+    u = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
+    rec, offered = learned.harvest(ctx_h, u, args.harvest_steps, args.cfl, capacity=args.harvest_cap)
+    del u
+    t_h = time.perf_counter() - t0
+    print(f"[bench] learned: {offered} interface records from {args.harvest_steps} steps ({t_h:.1f} s)",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    theta, hist = learned.train(rec, args.train_steps, batch=4096, lr=1e-3, seed=0,
+                                log_every=max(1, args.train_steps // 4))
+    torch.cuda.synchronize()
+    t_t = time.perf_counter() - t0
+    print(f"[bench] learned: trained {args.train_steps} Adam steps ({t_t:.1f} s), loss {hist[0][1]:.3e} -> "
+          f"{hist[-1][1]:.3e}", file=sys.stderr, flush=True)
+    del rec
+    ctx = make_ctx()
+    ctx.set_guess(ppmlr.GUESS_LEARNED, theta)
+    u = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
+    tiles = ctx.autotune(u, reps=3)
+    ctx.advance(u, args.warmup, args.cfl)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ctx.advance(u, args.steps, args.cfl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = ctx.stats()
+    zones = u[0].numel()
+    value = zones * args.steps / (ms / 1000.0)
+
+    def iters(s):
+        h = np.array(s["iters_hist"], dtype=np.int64)
+        return int((h * np.arange(32)).sum())
+
+    def prim(U):
+        U = U.double()
+        rho = U[0]
+        v2 = (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / (rho * rho)
+        b2 = U[4] ** 2 + U[5] ** 2 + U[6] ** 2
+        p = (5.0 / 3.0 - 1.0) * (U[7] - 0.5 * rho * v2 - 0.5 * b2)
+        return {"rho": rho, "p": p, "|B'|": torch.sqrt(b2)}
+
+    a, b = prim(u), prim(u_plain)
+    err = {k: float((a[k] - b[k]).abs().max() / b[k].abs().max()) for k in a}
+    return {
+        "value": value,
+        "unit": "zone-updates/s",
+        "ms_per_step": ms / args.steps,
+        "speedup_vs_fp32_plain": value / value_plain,
+        "tiles": tiles,
+        "newton_iterations": {"plain": iters(st_plain), "learned": iters(st)},
+        "selected_faces": st["guess_faces"],
+        "fallbacks": st["guess_fallbacks"],
+        "nonconverged": st["nonconverged"],
+        "max_rel_error_vs_fp32_plain": err,
+        "harvest": {"steps": args.harvest_steps, "records_offered": offered,
+                    "records_kept": min(offered, args.harvest_cap), "seconds": round(t_h, 2)},
+        "training": {"adam_steps": args.train_steps, "batch": 4096, "lr": 1e-3, "seconds": round(t_t, 2),
+                     "loss_first": hist[0][1], "loss_last": hist[-1][1]},
+    }
+
+
 def ensemble_leg(args):
     """The 32-member batched ensemble (uneven cubic grids 96^3..160^3, seeded
     solar-wind inputs), FP32, autotuned workgroup size, timed over
@@ -154,6 +235,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--harvest-steps", type=int, default=20)
+    ap.add_argument("--harvest-cap", type=int, default=10_000_000)
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -221,16 +306,21 @@ def main():
     avg = [kms[a] / kn[a] if kn[a] else 0.0 for a in range(3)]
     dom = int(np.argmax(avg))
     bytes_per_launch = 64.0 * zones            # 8 FP32 variables read + written
-    achieved = bytes_per_launch / (avg[dom] / 1000.0) / 1e9
+    gbs = bytes_per_launch / (avg[dom] / 1000.0) / 1e9
+    tflops = FLOPS_PER_ZONE_SWEEP * zones / (avg[dom] / 1000.0) / 1e12
     traffic, _ = load_traffic("f32")
     roofline = {
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "bound": "alu",
+        "achieved": round(tflops, 2),
+        "peak": FP32_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
         "traffic": traffic["bytes_per_launch"][str(dom)] if traffic else None,
         "kernel": f"sweep axis {'xyz'[dom]} (f32)",
+        "flops_per_zone_sweep": FLOPS_PER_ZONE_SWEEP,
+        "frac_of_unpacked_fp32": round(tflops / FP32_UNPACKED_TFLOPS, 4),
+        "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": bytes_per_launch},
         "avg_launch_ms": [round(a, 4) for a in avg],
         "launches": kn,
         "sum_kernel_ms_per_step": round(sum(kms) / args.steps, 4),
@@ -258,6 +348,9 @@ def main():
         "health": {"status": status, "finite": finite, "floor_hits": st["floor_hits"],
                    "nonconverged": st["nonconverged"], "simulated_time": ctx.time(u)},
     }
+    if not args.no_learned:
+        out["learned"] = learned_leg(args, setup, make_ctx, u, st, value)
+        torch.cuda.empty_cache()
     del u
     torch.cuda.empty_cache()
 

@@ -157,6 +157,20 @@ int block_threads(int P, int M) { return ((P * M + 63) / 64) * 64; }
 
 // Automatic tile: the number of pencils per workgroup that wastes the fewest
 // lanes (padding to whole waves plus ghost zones), within the thread budget.
+// LDS stride of a sweep launch with `threads` lanes: the smallest of the
+// compile-time strides 256, 384, ..., 1024 (steps of 128) that holds them and
+// whose two buffers fit the 160 KB LDS; 0 = the exact runtime stride (FP64
+// tiles above 896 lanes); -1 = does not fit.  A stride close to the
+// workgroup size leaves LDS for more resident workgroups per CU.
+int stride_for(int threads, int elem)
+{
+    if (threads > 1024) return -1;
+    const int sm = threads <= 256 ? 256 : (threads + 127) / 128 * 128;
+    if ((size_t)(kSlotsA + kSlotsB) * sm * elem <= 160 * 1024) return sm;
+    if ((size_t)(kSlotsA + kSlotsB) * threads * elem <= 160 * 1024 && elem == 8) return 0;
+    return -1;
+}
+
 int auto_tile(const ppmlr_ctx *c, int axis, int elem)
 {
     const int N = c->n[axis], M = N + 2 * kG;
@@ -167,9 +181,7 @@ int auto_tile(const ppmlr_ctx *c, int axis, int elem)
     for (int P = 1; P <= 16; ++P) {
         int thr = block_threads(P, M);
         if (thr > cap && P > 1) break;
-        int sm = thr <= 256 ? 256 : (thr <= 512 ? 512 : 1024);
-        size_t lds = (size_t)(kSlotsA + kSlotsB) * sm * elem;
-        if (lds > 160 * 1024 && (elem == 4 || P > 1)) break;
+        if (stride_for(block_threads(P, M), elem) < 0) break;
         int tiles_q = (nq + P - 1) / P;
         double cost = (double)thr * tiles_q / ((double)N * nq);  // lanes per useful zone
         if (cost < best_cost - 1e-9) { best_cost = cost; best = P; }
@@ -277,29 +289,23 @@ ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t 
     return hip_check(c, hipGetLastError(), "sweep launch");
 }
 
-// LDS stride of a launch: the smallest power of two >= the workgroup size
-// (256, 512, 1024) whose buffers fit the LDS; FP64 tiles above 512 threads use
-// the exact runtime stride instead.
-template <typename T>
-int lds_stride(int threads)
-{
-    int sm = threads <= 256 ? 256 : (threads <= 512 ? 512 : 1024);
-    if ((size_t)(kSlotsA + kSlotsB) * sm * sizeof(T) > 160 * 1024) return 0;
-    return sm;
-}
-
 template <int AX, typename T, bool STATS, bool FUSE>
 ppmlr_status launch_sm(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
 {
-    switch (lds_stride<T>(block_threads(a.P, a.M))) {
+    switch (stride_for(block_threads(a.P, a.M), (int)sizeof(T))) {
     case 256: return launch_one<AX, T, STATS, FUSE, 256>(c, a, st);
+    case 384: return launch_one<AX, T, STATS, FUSE, 384>(c, a, st);
     case 512: return launch_one<AX, T, STATS, FUSE, 512>(c, a, st);
+    case 640: return launch_one<AX, T, STATS, FUSE, 640>(c, a, st);
+    case 768: return launch_one<AX, T, STATS, FUSE, 768>(c, a, st);
+    case 896: return launch_one<AX, T, STATS, FUSE, 896>(c, a, st);
     case 1024:
         if constexpr (sizeof(T) == 4) return launch_one<AX, T, STATS, FUSE, 1024>(c, a, st);
-        else return launch_one<AX, T, STATS, FUSE, 0>(c, a, st);
-    default:
+        else return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
+    case 0:
         if constexpr (sizeof(T) == 8) return launch_one<AX, T, STATS, FUSE, 0>(c, a, st);
         else return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
+    default: return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
     }
 }
 
@@ -307,7 +313,8 @@ ppmlr_status launch_sm(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t s
 template <int AX, bool FUSE, int GUESS>
 ppmlr_status launch_guess(ppmlr_ctx *c, const ppmlr::SweepArgs<float> &a, hipStream_t st)
 {
-    switch (lds_stride<float>(block_threads(a.P, a.M))) {
+    const int thr = block_threads(a.P, a.M);
+    switch (thr <= 256 ? 256 : (thr <= 512 ? 512 : (thr <= 1024 ? 1024 : -1))) {
     case 256: return launch_one<AX, float, true, FUSE, 256, GUESS>(c, a, st);
     case 512: return launch_one<AX, float, true, FUSE, 512, GUESS>(c, a, st);
     case 1024: return launch_one<AX, float, true, FUSE, 1024, GUESS>(c, a, st);
@@ -939,10 +946,7 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
         for (int P = 1; P <= 32 && !e; ++P) {
             const int thr = block_threads(P, M);
             if (thr > 1024) break;
-            const int sm = thr <= 256 ? 256 : (thr <= 512 ? 512 : 1024);
-            if ((size_t)(kSlotsA + kSlotsB) * sm * elem > 160 * 1024 && !(elem == 8 && thr > 512 &&
-                (size_t)(kSlotsA + kSlotsB) * P * M * elem <= 160 * 1024))
-                continue;
+            if (stride_for(thr, (int)elem) < 0) continue;
             c->tile[axis] = P;
             e = hip_check(c, hipMemcpyAsync(scratch, s->u, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
             if (!e) e = do_sweep(c, &tmp, dt, nullptr, axis, false);   // warm-up

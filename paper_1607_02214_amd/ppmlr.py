@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libppmlr.so")
+# the in-tree build; PPMLR_LIB names another build of the same sources
+LIB_PATH = os.environ.get("PPMLR_LIB") or os.path.join(_HERE, "libppmlr.so")
 
 PPMLR_OK = 0
 PPMLR_EINVAL = -1
