@@ -278,7 +278,8 @@ template <int AX, typename T, bool STATS, bool FUSE, int SM, int GUESS = 0>
 ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
 {
     const int threads = block_threads(a.P, a.M);
-    const size_t lds = (size_t)(kSlotsA + kSlotsB) * (SM > 0 ? SM : a.S) * sizeof(T);
+    const int slots = (GUESS == ppmlr::kGuessPlain ? kSlotsA : ppmlr::kSlotsAGuess) + kSlotsB;
+    const size_t lds = (size_t)slots * (SM > 0 ? SM : a.S) * sizeof(T);
     const int blocks = 8 * a.tiles_per_xcd;
     auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM, GUESS>;
     if (lds > 64 * 1024) {

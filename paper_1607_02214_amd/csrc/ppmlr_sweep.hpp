@@ -27,7 +27,8 @@
 namespace ppmlr {
 
 constexpr int kG = 7;           // ghost zones per side
-constexpr int kSlotsA = 14;     // values per zone in LDS buffer A
+constexpr int kSlotsA = 16;     // values per zone in LDS buffer A
+constexpr int kSlotsAGuess = 19;  // buffer A of the learned / harvest sweeps (3 more face values)
 constexpr int kSlotsB = 8;      // values per zone in LDS buffer B
 constexpr int kStatWords = 37;  // iteration histogram [32], floors, nonconverged, nonphys,
                                 // learned-guess faces, learned-guess fallbacks
@@ -272,7 +273,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
                   "learned / harvest modes are FP32 sweeps with a compile-time stride and counters");
     const int S = SM > 0 ? SM : a.S;                      // LDS stride
     T *sA = reinterpret_cast<T *>(smem_raw);
-    T *sB = sA + kSlotsA * S;
+    T *sB = sA + (GUESS == kGuessPlain ? kSlotsA : kSlotsAGuess) * S;
     const int q0 = tq * a.P;
 
     const int tid = threadIdx.x;
@@ -392,36 +393,46 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     const T bnm = sA[8 * S + sm1], bnp = sA[8 * S + sp1];
     const T bln = sA[11 * S + sm1], bl1 = sA[12 * S + sm1], bl2 = sA[13 * S + sm1];  // left face
     const T Ptm = sA[9 * S + sm1], Ptp = sA[9 * S + sp1];
+    // Each zone limits its own slopes (CW84 Eq. 1.7-1.8) and hands them to
+    // the zone on its left through buffer B; the right-edge value then needs
+    // the neighbour's slope only.  The edges go to buffer A, slots 9..15
+    // (the face values of R1 there have been read by then).
     T edgeR[7];
+    T ftil = T(0);
     {
-        SlopeW<T> s0, s1;
+        SlopeW<T> s0;
         s0.init(dmm, dm, dmp);
-        s1.init(dm, dmp, dmp2);
         EdgeW<T> ew;
         ew.init(dmm, dm, dmp, dmp2);
+        T da0[7], apv[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            T am = sA[k * S + sm1], ap = sA[k * S + sp1], ap2 = sA[k * S + sp2];
-            T da0 = s0.slope(am, W[k], ap);
-            T da1 = s1.slope(W[k], ap, ap2);
-            edgeR[k] = ew.edge(W[k], ap, da0, da1);
+            const T am = sA[k * S + sm1];
+            apv[k] = sA[k * S + sp1];
+            da0[k] = s0.slope(am, W[k], apv[k]);
         }
-    }
-    T ftil = T(0);
-    if (a.flatten) {
-        T Ptm2 = sA[9 * S + sm2], Ptp2 = sA[9 * S + sp2];
-        T Pam = sA[10 * S + sm1], Pap = sA[10 * S + sp1];
-        T um = sA[1 * S + sm1], up = sA[1 * S + sp1];
-        T d1 = Ptp - Ptm, d2 = Ptp2 - Ptm2;
-        if (tabs(d1) > T(0.33) * tmin(Pap, Pam) && um > up) {
-            if (d2 != T(0)) ftil = tmax(T(0), tmin(T(1), T(10) * (Ar<T>::div(d1, d2) - T(0.75))));
-            else ftil = T(1);
+        if (a.flatten) {
+            T Ptm2 = sA[9 * S + sm2], Ptp2 = sA[9 * S + sp2];
+            T Pam = sA[10 * S + sm1], Pap = sA[10 * S + sp1];
+            T um = sA[1 * S + sm1], up = sA[1 * S + sp1];
+            T d1 = Ptp - Ptm, d2 = Ptp2 - Ptm2;
+            if (tabs(d1) > T(0.33) * tmin(Pap, Pam) && um > up) {
+                if (d2 != T(0)) ftil = tmax(T(0), tmin(T(1), T(10) * (Ar<T>::div(d1, d2) - T(0.75))));
+                else ftil = T(1);
+            }
         }
+        if (slot_ok) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) sB[k * S + tid] = da0[k];
+            sB[7 * S + tid] = ftil;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 7; ++k) edgeR[k] = ew.edge(W[k], apv[k], da0[k], sB[k * S + sp1]);
     }
     if (slot_ok) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) sB[k * S + tid] = edgeR[k];
-        sB[7 * S + tid] = ftil;
+        for (int k = 0; k < 7; ++k) sA[(9 + k) * S + tid] = edgeR[k];
     }
     __syncthreads();
 
@@ -434,7 +445,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     T pLc[7], pDc[7], p6c[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
-        T aL = sB[k * S + sm1];
+        T aL = sA[(9 + k) * S + sm1];
         parabola(W[k], aL, edgeR[k], fl, pLc[k], pDc[k], p6c[k]);
     }
     // tracing speeds (Lagrangian): normal pair C_n, Alfven pair C_A
@@ -516,9 +527,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             sA[7 * S + tid] = avgL(pLc[4], pDc[4], p6c[4], yA) + corrB1;
             sA[8 * S + tid] = avgL(pLc[5], pDc[5], p6c[5], yA) + corrB2;
             if (GUESS != kGuessPlain) {
-                sA[9 * S + tid] = r_;
-                sA[10 * S + tid] = T1;
-                sA[11 * S + tid] = T2;
+                sA[16 * S + tid] = r_;
+                sA[17 * S + tid] = T1;
+                sA[18 * S + tid] = T2;
             }
         }
     }
@@ -532,9 +543,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     T Rb1 = sA[7 * S + sp1], Rb2 = sA[8 * S + sp1];
     T RrN = LrN, RT1 = LT1, RT2 = LT2;
     if (GUESS != kGuessPlain && face_ok) {
-        RrN = sA[9 * S + sp1];
-        RT1 = sA[10 * S + sp1];
-        RT2 = sA[11 * S + sp1];
+        RrN = sA[16 * S + sp1];
+        RT1 = sA[17 * S + sp1];
+        RT2 = sA[18 * S + sp1];
     }
     if (!face_ok) {  // keep unused lanes trivial (no Newton iterations)
         RPt = LPt; Ru = Lu; RC = LC; Rk = Lk; Rr = Lr; Rv1 = Lv1; Rv2 = Lv2; Rb1 = Lb1; Rb2 = Lb2;
@@ -725,25 +736,32 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     __syncthreads();
 
     // ------------------------------------------------------------ R6
+    // slopes shared through buffer B as in R2; edges to buffer A, slots 8..14
     T redgeR[7];
     {
         const T vm = sA[7 * S + sm1], vp = sA[7 * S + sp1], vp2 = sA[7 * S + sp2];
-        SlopeW<T> s0, s1;
+        SlopeW<T> s0;
         s0.init(vm, dVL, vp);
-        s1.init(dVL, vp, vp2);
         EdgeW<T> ew;
         ew.init(vm, dVL, vp, vp2);
+        T da0[7], apv[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            T am = sA[k * S + sm1], ap = sA[k * S + sp1], ap2 = sA[k * S + sp2];
-            T da0 = s0.slope(am, QL[k], ap);
-            T da1 = s1.slope(QL[k], ap, ap2);
-            redgeR[k] = ew.edge(QL[k], ap, da0, da1);
+            const T am = sA[k * S + sm1];
+            apv[k] = sA[k * S + sp1];
+            da0[k] = s0.slope(am, QL[k], apv[k]);
         }
+        if (slot_ok) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) sB[k * S + tid] = da0[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 7; ++k) redgeR[k] = ew.edge(QL[k], apv[k], da0[k], sB[k * S + sp1]);
     }
     if (slot_ok) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) sB[k * S + tid] = redgeR[k];
+        for (int k = 0; k < 7; ++k) sA[(8 + k) * S + tid] = redgeR[k];
     }
     __syncthreads();
 
@@ -757,7 +775,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         const Frac<T> yR(delR * idVL), yL(-delL * idVL);
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            T aL = sB[k * S + sm1];
+            T aL = sA[(8 + k) * S + sm1];
             T cL, cD, c6;
             parabola(QL[k], aL, redgeR[k], fl, cL, cD, c6);
             if (wr) sA[k * S + tid] = delR * avgR(cL, cD, c6, yR);
