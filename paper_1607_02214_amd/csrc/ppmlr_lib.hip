@@ -213,6 +213,7 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     std::memset(&a, 0, sizeof(a));
     a.u = u;
     a.vol = (long long)nx * ny * nz;
+    for (int k = 0; k < 8; ++k) a.var[k] = u + (size_t)k * a.vol;
     a.N = N;
     a.M = M;
     a.P = P;
@@ -224,6 +225,7 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     a.nq = c->n[qax];
     a.nr = c->n[rax];
     a.tiles_q = (a.nq + P - 1) / P;
+    a.inv_div = 1.0f / (float)(axis == 0 ? M : P);
     a.ntiles = a.tiles_q * a.nr;
     const T *dummy;
     tabs(axis, a.dx, a.xc, a.xf, dummy, dummy);

@@ -65,6 +65,8 @@ struct SweepArgs {
     int P;                      // pencils per workgroup
     int S;                      // LDS slots = P * M
     long long stride_n, stride_q, stride_r;   // element strides
+    float inv_div;              // 1 / M (x sweep) or 1 / P (y, z): lane -> (pencil, zone)
+    T *var[8];                  // u + k * vol: base of each conserved variable
     int nq, nr;                 // pencils along q (memory-fastest transverse) and r
     int tiles_q, ntiles, tiles_per_xcd;
     int group_q;                // tiles along q taken together before stepping r (>= 1)
@@ -282,8 +284,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     const int Suse = a.S, M = a.M, N = a.N, P = a.P;
     const bool slot_ok = tid < Suse;
     int p, i;
-    if (AX == 0) { p = tid / M; i = tid - p * M; }       // zones of a pencil adjacent
-    else { i = tid / P; p = tid - i * P; }                // pencils adjacent (coalesced)
+    // tid / divisor as floor((tid + 1/2) * (1/divisor)): exact for tid < 2^12
+    // and divisors up to 2^11 (the distance to the next integer, >= 1/(2 div),
+    // exceeds the rounding error, < tid * 2^-23 / div)
+    const int qd = (int)(((float)tid + 0.5f) * a.inv_div);
+    if (AX == 0) { p = qd; i = tid - p * M; }             // zones of a pencil adjacent
+    else { i = qd; p = tid - i * P; }                     // pencils adjacent (coalesced)
     const int d = (AX == 0) ? 1 : P;                      // slot offset of zone i+1
     const int q = q0 + p;
     const bool pen = slot_ok && q < a.nq;
@@ -304,7 +310,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     if (AX == 1) { j1 = r; j2 = qq; c1 = a.xc_r[r]; c2 = a.xc_q[qq]; }
     else { j1 = qq; j2 = r; c1 = a.xc_q[qq]; c2 = a.xc_r[r]; }
     (void)j1; (void)j2;
-    const long long base = (long long)qq * a.stride_q + (long long)r * a.stride_r;
+    // 32-bit element offsets within one variable (at most 1010 zones per axis,
+    // so a variable holds fewer than 2^31 elements); each variable's base
+    // pointer is uniform
+    const unsigned int base = (unsigned int)(qq * (int)a.stride_q + r * (int)a.stride_r);
 
     // ------------------------------------------------------------ R1
     const int ic = i < M ? i : M - 1;
@@ -332,15 +341,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     T Q[8];
     constexpr int kn = AX, k1 = (AX + 1) % 3, k2 = (AX + 2) % 3;
     if (pen && !inflow_zone) {
-        const T *u = a.u + base + (long long)src * a.stride_n;
-        Q[0] = u[0];
-        Q[1] = u[(1 + kn) * a.vol];
-        Q[2] = u[(1 + k1) * a.vol];
-        Q[3] = u[(1 + k2) * a.vol];
-        Q[4] = u[(4 + kn) * a.vol];
-        Q[5] = u[(4 + k1) * a.vol];
-        Q[6] = u[(4 + k2) * a.vol];
-        Q[7] = u[7 * a.vol];
+        const unsigned int o = base + (unsigned int)(src * (int)a.stride_n);
+        Q[0] = a.var[0][o];
+        Q[1] = a.var[1 + kn][o];
+        Q[2] = a.var[1 + k1][o];
+        Q[3] = a.var[1 + k2][o];
+        Q[4] = a.var[4 + kn][o];
+        Q[5] = a.var[4 + k1][o];
+        Q[6] = a.var[4 + k2][o];
+        Q[7] = a.var[7][o];
     } else if (pen) {
         // inflow ghost: primitive inflow state with B' = B_in - B_d(centre)
         T vn, v1, v2, Bn, B1, B2;
@@ -821,9 +830,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
                 out[7] = a.inner_E;
             }
         }
-        T *uo = a.u + base + (long long)g * a.stride_n;
+        const unsigned int o = base + (unsigned int)(g * (int)a.stride_n);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) uo[v * a.vol] = out[v];
+        for (int v = 0; v < 8; ++v) a.var[v][o] = out[v];
         if (FUSE_CFL && !masked) {
             // signal speed of the updated zone, for the next step's dt (the
             // maximum is reduced in FP64)
