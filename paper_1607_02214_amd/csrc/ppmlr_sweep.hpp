@@ -7,16 +7,18 @@
 // Execution model: one thread per zone, a workgroup owns P whole pencils
 // (N interior zones + 7 ghosts per side each), so the update is done in place
 // and every stencil is served from LDS.  Successive stages exchange only what
-// a neighbour needs, through two LDS buffers used alternately (A, B) with one
-// barrier per exchange:
-//   R1 load + primitives                         -> A
-//   R2 edge values (mass coordinate), shock test  A -> B
-//   R3 parabolas, tracing, interface states       B -> A
-//   R4 Riemann solves, Lagrangian fluxes          A -> B
-//   R5 Lagrangian zone contents                   B -> A
-//   R6 remap edge values (volume coordinate)      A -> B
-//   R7 remap parabolas, donor-cell fluxes         B -> A
-//   R8 conservative update, sources, store        A
+// a neighbour needs, through two LDS buffers (A, B) with one barrier per
+// exchange:
+//   R1 load + primitives                                  -> A
+//   R2 limited slopes (mass coordinate), shock test   A -> B
+//      edge values                                   A, B -> A (slots 9..15)
+//   R3 parabolas, tracing, interface states       A, B -> A
+//   R4 Riemann solves, Lagrangian fluxes              A -> B
+//   R5 Lagrangian zone contents                       B -> A
+//   R6 limited slopes (volume coordinate)             A -> B
+//      remap edge values                           A, B -> A (slots 8..14)
+//   R7 remap parabolas, donor-cell fluxes             A -> A
+//   R8 conservative update, sources, store            A
 // The pencil axis is a template parameter so that all component indexing is
 // static (no private arrays with dynamic indices).
 #pragma once
