@@ -145,10 +145,12 @@ __device__ __forceinline__ void forward_wave(const unsigned short *F, const unsi
             const float *b1 = theta + kOffB1 + mt * 16 + 4 * q;
             h1[mt] = pack4(gelu(z[0] + b1[0]), gelu(z[1] + b1[1]), gelu(z[2] + b1[2]), gelu(z[3] + b1[3]));
         }
-        // layer 2: Z2^T = W2^T H1^T
+        // layer 2: Z2^T = W2^T H1^T (weight loads kept per output tile, so
+        // that at most four fragments are in flight)
         bf16x4 h2[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
+            asm volatile("" ::: "memory");
             f32x4 acc = zero;
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt) acc = mfma(load_frag(frag, kTA2 + mt * 4 + kt, lane), h1[kt], acc);

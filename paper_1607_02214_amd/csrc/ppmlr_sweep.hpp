@@ -260,6 +260,35 @@ __device__ inline void wave_hist(unsigned int *s_hist, bool counted, int bin)
 // One tile (P whole pencils) of a sweep, executed by one workgroup.  tq, r:
 // tile position (q tiles of P pencils, r the slow transverse index); dt: the
 // time step; cfl_max: target of the fused signal-speed maximum (FUSE_CFL);
+// Inputs of the learned guess for one face (see the Riemann block of
+// sweep_tile): sides s = (rho, u, v_t1, v_t2, B_t1, B_t2, P), normalised by
+// the pair means.  Returns whether the face is selected (strong pressure or
+// velocity jump); Pbar and cbar are the mean pressure and sqrt(P/rho).
+template <typename T>
+__device__ inline bool guess_features(const T *L, const T *R, T gate_p, T gate_u, T *feat, T &Pbar, T &cbar)
+{
+    const T rbar = T(0.5) * (L[0] + R[0]);
+    Pbar = T(0.5) * (L[6] + R[6]);
+    const T irb = Ar<T>::rcp(rbar), iPb = Ar<T>::rcp(Pbar);
+    cbar = Ar<T>::sqrt_(Pbar * irb);
+    const T icb = Ar<T>::rcp(cbar), ibs = Ar<T>::rsqrt(Pbar);
+    const T ub = T(0.5) * (L[1] + R[1]), v1b = T(0.5) * (L[2] + R[2]), v2b = T(0.5) * (L[3] + R[3]);
+    const T *side[2] = {L, R};
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        const T *x = side[sd];
+        T *f = feat + 7 * sd;
+        f[0] = x[0] * irb;
+        f[1] = (x[1] - ub) * icb;
+        f[2] = (x[2] - v1b) * icb;
+        f[3] = (x[3] - v2b) * icb;
+        f[4] = x[4] * ibs;
+        f[5] = x[5] * ibs;
+        f[6] = x[6] * iPb;
+    }
+    return tabs(R[6] - L[6]) > gate_p * tmin(L[6], R[6]) || tabs(R[1] - L[1]) > gate_u * cbar;
+}
+
 // stat_slot: which copy of the counters this workgroup adds to.
 // SM: LDS stride per stored value (a power of two >= P*M, so that every LDS
 // access uses an immediate offset), or 0 for a runtime stride P*M.
@@ -549,11 +578,65 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     // ------------------------------------------------------------ R4
     // face i+1/2 between this zone (L) and zone i+1 (R)
     const bool face_ok = pen && i >= 3 && i <= M - 5;
+    // Learned guess: faces with a strong jump are compacted per workgroup into
+    // buffer B (free until the fluxes are written) and run through the network
+    // 64 at a time on the matrix cores.  This pass comes before the solver's
+    // right states are loaded, so that they do not occupy registers next to
+    // the network's; they are read again from LDS below.
+    bool lg_gate = false, lg_have = false;   // selected; network output available
+    T lg_y = T(0), lg_Pbar = T(1);
+    if constexpr (GUESS == kGuessLearned) {
+        constexpr int kCap = ((8 * SM * (int)sizeof(T)) / 40) / 64 * 64;
+        const int lane = tid & 63;
+        unsigned short *F = reinterpret_cast<unsigned short *>(sB);
+        float *Yo = reinterpret_cast<float *>(F + kCap * 16);
+        int slot = 0;
+        {
+            const T Pd_ = T(0.5) * (bf1 * bf1 + bf2 * bf2);
+            const T Ls[7] = {LrN, Lu, Lv1, Lv2, LT1, LT2, LPt + Pd_};
+            T Rs[7];
+            if (face_ok) {
+                Rs[0] = sA[16 * S + sp1]; Rs[1] = sA[1 * S + sp1]; Rs[2] = sA[5 * S + sp1];
+                Rs[3] = sA[6 * S + sp1]; Rs[4] = sA[17 * S + sp1]; Rs[5] = sA[18 * S + sp1];
+                Rs[6] = sA[0 * S + sp1] + Pd_;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) Rs[k] = Ls[k];
+            }
+            T feat[14], cbar_;
+            lg_gate = face_ok && guess_features(Ls, Rs, a.gate_p, a.gate_u, feat, lg_Pbar, cbar_);
+            const unsigned long long bal = __ballot(lg_gate);
+            int base = 0;
+            if (lane == 0 && bal) base = (int)atomicAdd(&s_guess[0], (unsigned int)__popcll(bal));
+            base = __shfl(base, 0);
+            slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+            if (lg_gate && slot < kCap) {
+                unsigned int w[8];
+#pragma unroll
+                for (int k = 0; k < 7; ++k)
+                    w[k] = (unsigned int)mlp::f2bf((float)feat[2 * k]) |
+                           ((unsigned int)mlp::f2bf((float)feat[2 * k + 1]) << 16);
+                w[7] = 0u;
+                uint4 *dst = reinterpret_cast<uint4 *>(F + slot * 16);
+                dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+                dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+            }
+        }
+        if (STATS) wave_add(&s_stat[35], lg_gate);
+        __syncthreads();
+        const int nf = min((int)s_guess[0], kCap);
+        for (int b0 = (tid >> 6) * 64; b0 < nf; b0 += (int)(blockDim.x >> 6) * 64)
+            mlp::forward_wave(F + b0 * 16, a.mlp_frag, a.mlp_theta, Yo + b0 * 2, 2);
+        __syncthreads();
+        lg_have = lg_gate && slot < kCap;
+        if (lg_have) lg_y = (T)Yo[slot * 2];
+        __syncthreads();   // buffer B is written with the fluxes next
+    }
     T RPt = sA[0 * S + sp1], Ru = sA[1 * S + sp1], RC = sA[2 * S + sp1], Rk = sA[3 * S + sp1];
     T Rr = sA[4 * S + sp1], Rv1 = sA[5 * S + sp1], Rv2 = sA[6 * S + sp1];
     T Rb1 = sA[7 * S + sp1], Rb2 = sA[8 * S + sp1];
     T RrN = LrN, RT1 = LT1, RT2 = LT2;
-    if (GUESS != kGuessPlain && face_ok) {
+    if (GUESS == kGuessHarvest && face_ok) {
         RrN = sA[16 * S + sp1];
         RT1 = sA[17 * S + sp1];
         RT2 = sA[18 * S + sp1];
@@ -578,60 +661,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         // sqrt(P)).  Outputs: (P* - P0) / P and (u* - u0) / c.
         bool gate = false;
         T feat[14], Pbar = T(1), cbar = T(1);
-        if (GUESS != kGuessPlain) {
-            const T rbar = T(0.5) * (LrN + RrN);
-            Pbar = T(0.5) * (PL + PR);
-            const T irb = Ar<T>::rcp(rbar), iPb = Ar<T>::rcp(Pbar);
-            cbar = Ar<T>::sqrt_(Pbar * irb);
-            const T icb = Ar<T>::rcp(cbar), ibs = Ar<T>::rsqrt(Pbar);
-            const T ub = T(0.5) * (Lu + Ru), v1b = T(0.5) * (Lv1 + Rv1), v2b = T(0.5) * (Lv2 + Rv2);
-            gate = face_ok && (tabs(PR - PL) > a.gate_p * tmin(PL, PR) || tabs(Ru - Lu) > a.gate_u * cbar);
-            feat[0] = LrN * irb; feat[1] = (Lu - ub) * icb; feat[2] = (Lv1 - v1b) * icb; feat[3] = (Lv2 - v2b) * icb;
-            feat[4] = LT1 * ibs; feat[5] = LT2 * ibs; feat[6] = PL * iPb;
-            feat[7] = RrN * irb; feat[8] = (Ru - ub) * icb; feat[9] = (Rv1 - v1b) * icb; feat[10] = (Rv2 - v2b) * icb;
-            feat[11] = RT1 * ibs; feat[12] = RT2 * ibs; feat[13] = PR * iPb;
+        if (GUESS == kGuessHarvest) {
+            const T Ls[7] = {LrN, Lu, Lv1, Lv2, LT1, LT2, PL};
+            const T Rs[7] = {RrN, Ru, Rv1, Rv2, RT1, RT2, PR};
+            gate = face_ok && guess_features(Ls, Rs, a.gate_p, a.gate_u, feat, Pbar, cbar);
             if (STATS) wave_add(&s_stat[35], gate);
         }
-        if constexpr (GUESS == kGuessLearned) {
-            // Compact the selected faces of the workgroup into buffer B
-            // (free until the fluxes are written), run the network on them
-            // 64 at a time on the matrix cores, and start Newton from its
-            // pressure where that is finite and above the floor.
-            constexpr int kCap = ((8 * SM * (int)sizeof(T)) / 40) / 64 * 64;
-            const int lane = tid & 63;
-            const unsigned long long bal = __ballot(gate);
-            int base = 0;
-            if (lane == 0 && bal) base = (int)atomicAdd(&s_guess[0], (unsigned int)__popcll(bal));
-            base = __shfl(base, 0);
-            const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
-            unsigned short *F = reinterpret_cast<unsigned short *>(sB);
-            float *Yo = reinterpret_cast<float *>(F + kCap * 16);
-            if (gate && slot < kCap) {
-                unsigned int w[8];
-#pragma unroll
-                for (int k = 0; k < 7; ++k)
-                    w[k] = (unsigned int)mlp::f2bf((float)feat[2 * k]) |
-                           ((unsigned int)mlp::f2bf((float)feat[2 * k + 1]) << 16);
-                w[7] = 0u;
-                uint4 *dst = reinterpret_cast<uint4 *>(F + slot * 16);
-                dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-                dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
-            }
-            __syncthreads();
-            const int nf = min((int)s_guess[0], kCap);
-            for (int b0 = (tid >> 6) * 64; b0 < nf; b0 += (int)(blockDim.x >> 6) * 64)
-                mlp::forward_wave(F + b0 * 16, a.mlp_frag, a.mlp_theta, Yo + b0 * 2, 2);
-            __syncthreads();
+        if (GUESS == kGuessLearned) {
             bool used = false;
-            if (gate && slot < kCap) {
-                const T Pg = P + Pbar * (T)Yo[slot * 2];
+            if (lg_have) {
+                const T Pg = P + lg_Pbar * lg_y;
                 if (__builtin_isfinite(Pg) && Pg > Pfloor) {
                     P = Pg;
                     used = true;
                 }
             }
-            if (STATS) wave_add(&s_stat[36], gate && !used);
-            __syncthreads();   // buffer B is written with the fluxes next
+            if (STATS) wave_add(&s_stat[36], lg_gate && !used);
         }
         int it = 0;
         bool conv = true;
