@@ -685,22 +685,30 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         // star velocities, so that a large bulk velocity does not bury it in
         // rounding (same quantity; matters in single precision at high Mach).
         const T duRL = Ru - Lu;
-        T jL, ZL, ZR, dP, mis;
+        // Shock impedances W_s = C_s sqrt(q_s), q_s = 1 + k_s (P - P_s) / P_s,
+        // and Z_s = 2 W_s^3 / (W_s^2 + C_s^2), carried as 1/sqrt(q_s) and
+        // 1/Z_s = (q_s + 1) / (2 C_s q_s^{3/2}): two reciprocal square roots
+        // and one reciprocal per iteration.  Then dP = -mis Z_L Z_R / (Z_L + Z_R)
+        // = -mis / (1/Z_L + 1/Z_R).
+        const T kL = Lk * iPL, kR = Rk * iPR;
+        const T iCL = Ar<T>::rcp(LC), iCR = Ar<T>::rcp(RC);
+        T jL, gL, ig, dP, mis;
         for (;;) {
-            T WL = LC * Ar<T>::sqrt_(T(1) + Lk * (P - LPt) * iPL);
-            T WR = RC * Ar<T>::sqrt_(T(1) + Rk * (P - RPt) * iPR);
-            jL = (P - LPt) * Ar<T>::rcp(WL);
-            mis = duRL + (P - RPt) * Ar<T>::rcp(WR) + jL;
-            ZL = T(2) * WL * WL * WL * Ar<T>::rcp(WL * WL + LC * LC);
-            ZR = T(2) * WR * WR * WR * Ar<T>::rcp(WR * WR + RC * RC);
-            dP = -ZL * ZR * mis * Ar<T>::rcp(ZL + ZR);
+            const T qL = T(1) + kL * (P - LPt), qR = T(1) + kR * (P - RPt);
+            const T sL = Ar<T>::rsqrt(qL), sR = Ar<T>::rsqrt(qR);
+            jL = (P - LPt) * sL * iCL;
+            mis = duRL + (P - RPt) * sR * iCR + jL;
+            gL = T(0.5) * (qL + T(1)) * (sL * sL) * (sL * iCL);
+            const T gR = T(0.5) * (qR + T(1)) * (sR * sR) * (sR * iCR);
+            ig = Ar<T>::rcp(gL + gR);
+            dP = -mis * ig;
             if (tabs(dP) <= tol * (P + Pd)) break;
             if (it >= a.max_iter) { conv = false; break; }
             P = tmax(P + dP, Pfloor);
             ++it;
         }
         Pst = tmax(P + dP, Pfloor);
-        ust = (Lu - jL) + ZR * mis * Ar<T>::rcp(ZL + ZR);
+        ust = (Lu - jL) + mis * gL * ig;
         if constexpr (GUESS == kGuessHarvest) {
             // record the selected faces: inputs, targets and the solver's own
             // scalars (for checks against an independent solver)
