@@ -57,6 +57,14 @@ template <> struct Ar<float> {
 template <typename T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
 template <typename T> __device__ inline T tabs(T a) { return a < T(0) ? -a : a; }
+// IEEE min / |x| / copysign in the type's own precision (the unsuffixed
+// builtins are the double versions and would convert FP32 operands)
+__device__ inline float fmin_(float a, float b) { return __builtin_fminf(a, b); }
+__device__ inline double fmin_(double a, double b) { return __builtin_fmin(a, b); }
+__device__ inline float fabs_(float a) { return __builtin_fabsf(a); }
+__device__ inline double fabs_(double a) { return __builtin_fabs(a); }
+__device__ inline float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
+__device__ inline double copysign_(double a, double b) { return __builtin_copysign(a, b); }
 template <typename T> __device__ inline T tsgn(T a) { return a > T(0) ? T(1) : (a < T(0) ? T(-1) : T(0)); }
 
 template <typename T>
@@ -190,8 +198,8 @@ struct SlopeW {
         T dp = ap - a0;
         T dm = a0 - am;
         T da = A * dp + B * dm;
-        T m = __builtin_fmin(__builtin_fmin(__builtin_fabs(T(0.5) * da), __builtin_fabs(dm)), __builtin_fabs(dp));
-        T r = __builtin_copysign(m + m, dp);
+        T m = fmin_(fmin_(fabs_(T(0.5) * da), fabs_(dm)), fabs_(dp));
+        T r = copysign_(m + m, dp);
         return (dp * dm > T(0)) ? r : T(0);
     }
 };
