@@ -101,7 +101,11 @@ void ppmlr_default_options(ppmlr_options *opt);
 /* Create a context for one grid.  gamma: adiabatic index (Section II: 5/3).
  * coords: host face coordinates, copied to the device.  opt: NULL for the
  * defaults.  Returns EINVAL for a bad grid (counts, non-increasing faces,
- * mismatched periodic sides, non-periodic axis shorter than 7 zones). */
+ * mismatched periodic sides, non-periodic axis shorter than 7 zones, more
+ * than 1010 zones along an axis: a pencil and its 14 ghosts must fit one
+ * 1024-lane workgroup).  Every call that takes a state also returns EINVAL
+ * if one variable of it (nx ny nz elements) exceeds 4 GiB: FP32 grids up to
+ * 1010^3 zones, FP64 up to 2^29 zones. */
 ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coords *coords,
                           const ppmlr_options *opt, ppmlr_ctx **out);
 void ppmlr_destroy(ppmlr_ctx *ctx);

@@ -360,6 +360,9 @@ ppmlr_status check_state(ppmlr_ctx *c, const ppmlr_state *s)
     if (!c) return PPMLR_EINVAL;
     if (!s || !s->u) return fail(c, PPMLR_EINVAL, "null state");
     if (s->dtype != PPMLR_F32 && s->dtype != PPMLR_F64) return fail(c, PPMLR_EINVAL, "bad dtype");
+    // the sweeps address each variable with 32-bit byte offsets
+    const unsigned long long vbytes = (unsigned long long)c->n[0] * c->n[1] * c->n[2] * (s->dtype == PPMLR_F64 ? 8 : 4);
+    if (vbytes >= (1ull << 32)) return fail(c, PPMLR_EINVAL, "one variable of the state exceeds 4 GiB");
     return PPMLR_OK;
 }
 

@@ -57,6 +57,17 @@ template <> struct Ar<float> {
 template <typename T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
 template <typename T> __device__ inline T tabs(T a) { return a < T(0) ? -a : a; }
+// Element i of an array at a uniform base address, addressed by a 32-bit byte
+// offset (every array the sweep reads is below 4 GiB), so that the load or
+// store takes the scalar-base + vector-offset form.
+template <typename T> __device__ inline T &elem(T *base, unsigned int i)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (unsigned int)sizeof(T));
+}
+template <typename T> __device__ inline const T &elem(const T *base, unsigned int i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (unsigned int)sizeof(T));
+}
 // IEEE min / |x| / copysign in the type's own precision (the unsuffixed
 // builtins are the double versions and would convert FP32 operands)
 __device__ inline float fmin_(float a, float b) { return __builtin_fminf(a, b); }
@@ -346,19 +357,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     int j1, j2;
     T c1, c2;
     // q is t1 for the x and z sweeps, t2 for the y sweep
-    if (AX == 1) { j1 = r; j2 = qq; c1 = a.xc_r[r]; c2 = a.xc_q[qq]; }
-    else { j1 = qq; j2 = r; c1 = a.xc_q[qq]; c2 = a.xc_r[r]; }
+    if (AX == 1) { j1 = r; j2 = qq; c1 = elem(a.xc_r, r); c2 = elem(a.xc_q, qq); }
+    else { j1 = qq; j2 = r; c1 = elem(a.xc_q, qq); c2 = elem(a.xc_r, r); }
     (void)j1; (void)j2;
-    // 32-bit element offsets within one variable (at most 1010 zones per axis,
-    // so a variable holds fewer than 2^31 elements); each variable's base
-    // pointer is uniform
+    // 32-bit element offsets within one variable (the host keeps a variable
+    // below 4 GiB); each variable's base pointer is uniform
     const unsigned int base = (unsigned int)(qq * (int)a.stride_q + r * (int)a.stride_r);
 
     // ------------------------------------------------------------ R1
     const int ic = i < M ? i : M - 1;
-    const T dxi = a.dx[ic];
-    const T xci = a.xc[ic];
-    const T xfr = a.xf[ic + 1];
+    const T dxi = elem(a.dx, ic);
+    const T xci = elem(a.xc, ic);
+    const T xfr = elem(a.xf, ic + 1);
     int src = g;
     bool inflow_zone = false;
     if (g < 0) {
@@ -381,14 +391,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     constexpr int kn = AX, k1 = (AX + 1) % 3, k2 = (AX + 2) % 3;
     if (pen && !inflow_zone) {
         const unsigned int o = base + (unsigned int)(src * (int)a.stride_n);
-        Q[0] = a.var[0][o];
-        Q[1] = a.var[1 + kn][o];
-        Q[2] = a.var[1 + k1][o];
-        Q[3] = a.var[1 + k2][o];
-        Q[4] = a.var[4 + kn][o];
-        Q[5] = a.var[4 + k1][o];
-        Q[6] = a.var[4 + k2][o];
-        Q[7] = a.var[7][o];
+        Q[0] = elem(a.var[0], o);
+        Q[1] = elem(a.var[1 + kn], o);
+        Q[2] = elem(a.var[1 + k1], o);
+        Q[3] = elem(a.var[1 + k2], o);
+        Q[4] = elem(a.var[4 + kn], o);
+        Q[5] = elem(a.var[4 + k1], o);
+        Q[6] = elem(a.var[4 + k2], o);
+        Q[7] = elem(a.var[7], o);
     } else if (pen) {
         // inflow ghost: primitive inflow state with B' = B_in - B_d(centre)
         T vn, v1, v2, Bn, B1, B2;
@@ -867,7 +877,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         T nbn = bn, nb1 = nw[4], nb2 = nw[5];
         if (a.janhunen) {
             // -v div B' source, split: n-derivative of B'_n, pre-sweep velocity
-            const T xm = a.xc[i - 1], xp = a.xc[i + 1];
+            const T xm = elem(a.xc, i - 1), xp = elem(a.xc, i + 1);
             const T divn = (bnp - bnm) * Ar<T>::rcp(xp - xm);
             nbn -= dt * un * divn;
             nb1 -= dt * v1 * divn;
@@ -895,7 +905,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         }
         const unsigned int o = base + (unsigned int)(g * (int)a.stride_n);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) a.var[v][o] = out[v];
+        for (int v = 0; v < 8; ++v) elem(a.var[v], o) = out[v];
         if (FUSE_CFL && !masked) {
             // signal speed of the updated zone, for the next step's dt (the
             // maximum is reduced in FP64)
@@ -921,7 +931,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             const T b2 = (Bx * Bx + By * By + Bz * Bz) * ir;
             const T s2 = a2 + b2;
             const T q4 = T(4) * a2 * ir;
-            const T wx = a.dxw_x[ix], wy = a.dxw_y[iy], wz = a.dxw_z[iz];
+            const T wx = elem(a.dxw_x, ix), wy = elem(a.dxw_y, iy), wz = elem(a.dxw_z, iz);
             T sp = T(0);
             {
                 T disc = tmax(s2 * s2 - q4 * Bx * Bx, T(0));
