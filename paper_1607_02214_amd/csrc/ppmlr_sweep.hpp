@@ -72,6 +72,8 @@ template <typename T> __device__ inline const T &elem(const T *base, unsigned in
 // builtins are the double versions and would convert FP32 operands)
 __device__ inline float fmin_(float a, float b) { return __builtin_fminf(a, b); }
 __device__ inline double fmin_(double a, double b) { return __builtin_fmin(a, b); }
+__device__ inline float fmax_(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ inline double fmax_(double a, double b) { return __builtin_fmax(a, b); }
 __device__ inline float fabs_(float a) { return __builtin_fabsf(a); }
 __device__ inline double fabs_(double a) { return __builtin_fabs(a); }
 __device__ inline float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
@@ -222,22 +224,29 @@ struct Frac {
     __device__ inline explicit Frac(T y) : h(T(0.5) * y), c(T(1) - (T(2) / T(3)) * y) {}
 };
 
-// Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity
-// (written with selects: at a local extremum both edges take the zone
-// average; otherwise the edge on the far side of an overshooting parabola is
-// moved so that the parabola stays monotone).
+// Median of three.
+__device__ inline float med3_(float x, float y, float z) { return __builtin_amdgcn_fmed3f(x, y, z); }
+__device__ inline double med3_(double x, double y, double z)
+{
+    return fmax_(fmin_(x, y), fmin_(fmax_(x, y), z));
+}
+
+// Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity.  At a
+// local extremum both edges take the zone average; otherwise the edge on the
+// far side of an overshooting parabola is moved to 3a - 2a_other.  Both rules
+// are one median each: for a monotone profile (say a_L < a < a_R) the
+// overshoot test a6 > dA reads a_L < 3a - 2a_R, so the new left edge is
+// max(a_L, 3a - 2a_R) = med(a_L, 3a - 2a_R, a) (a is the largest of the
+// three); at an extremum 3a - 2a_R lies beyond a on the far side from a_L, so
+// the median is a.  Likewise on the right with a_L and a_R exchanged.
 template <typename T>
 __device__ inline void parabola(T a, T aL, T aR, T f, T &oL, T &oD, T &o6)
 {
     aL = aL + f * (a - aL);
     aR = aR + f * (a - aR);
-    const T dA = aR - aL;
-    const T a6 = T(6) * (a - T(0.5) * (aL + aR));
-    const bool ext = (aR - a) * (a - aL) <= T(0);
-    const bool fixL = dA * a6 > dA * dA;
-    const bool fixR = !fixL && (-dA * dA > dA * a6);
-    const T nL = ext ? a : (fixL ? T(3) * a - T(2) * aR : aL);
-    const T nR = ext ? a : (fixR ? T(3) * a - T(2) * aL : aR);
+    const T a3 = T(3) * a;
+    const T nL = med3_(aL, a3 - T(2) * aR, a);
+    const T nR = med3_(aR, a3 - T(2) * aL, a);
     oL = nL;
     oD = nR - nL;
     o6 = T(6) * (a - T(0.5) * (nL + nR));
