@@ -193,10 +193,32 @@ struct EdgeW {
     }
 };
 
+// Median of three.
+__device__ inline float med3_(float x, float y, float z) { return __builtin_amdgcn_fmed3f(x, y, z); }
+__device__ inline double med3_(double x, double y, double z)
+{
+    return fmax_(fmin_(x, y), fmin_(fmax_(x, y), z));
+}
+
+// Eq. 1.8 limiter: sgn(da) min(|da|, 2|dm|, 2|dp|) where dm and dp share a
+// sign, else zero.  When they share a sign da shares it too (the weights of
+// Eq. 1.7 are positive).  In single precision this is two medians: med(dm,
+// dp, 0) is the one-sided difference nearer zero when the signs agree and
+// zero otherwise, and med(da, 2 med(dm, dp, 0), 0) clips da to it.
+__device__ inline float limit_slope(float da, float dm, float dp)
+{
+    const float mm = med3_(dm, dp, 0.0f);
+    return med3_(da, mm + mm, 0.0f);
+}
+__device__ inline double limit_slope(double da, double dm, double dp)
+{
+    double m = fmin_(fmin_(fabs_(0.5 * da), fabs_(dm)), fabs_(dp));
+    double r = copysign_(m + m, dp);
+    return (dp * dm > 0.0) ? r : 0.0;
+}
+
 // Average slope times width in zone j on widths wm, w0, wp (CW84 Eq. 1.7),
-// da = A (a_{j+1} - a_j) + B (a_j - a_{j-1}), limited by Eq. 1.8.  When the
-// two one-sided differences share a sign, da shares it too (A, B > 0), so
-// sgn(da) min(|da|, 2|dm|, 2|dp|) = sgn(dp) 2 min(|da|/2, |dm|, |dp|).
+// da = A (a_{j+1} - a_j) + B (a_j - a_{j-1}), limited by Eq. 1.8.
 template <typename T>
 struct SlopeW {
     T A, B;
@@ -210,10 +232,7 @@ struct SlopeW {
     {
         T dp = ap - a0;
         T dm = a0 - am;
-        T da = A * dp + B * dm;
-        T m = fmin_(fmin_(fabs_(T(0.5) * da), fabs_(dm)), fabs_(dp));
-        T r = copysign_(m + m, dp);
-        return (dp * dm > T(0)) ? r : T(0);
+        return limit_slope(A * dp + B * dm, dm, dp);
     }
 };
 
@@ -223,13 +242,6 @@ struct Frac {
     T h, c;   // y/2 and 1 - 2y/3
     __device__ inline explicit Frac(T y) : h(T(0.5) * y), c(T(1) - (T(2) / T(3)) * y) {}
 };
-
-// Median of three.
-__device__ inline float med3_(float x, float y, float z) { return __builtin_amdgcn_fmed3f(x, y, z); }
-__device__ inline double med3_(double x, double y, double z)
-{
-    return fmax_(fmin_(x, y), fmin_(fmax_(x, y), z));
-}
 
 // Flattening toward the zone average, then CW84 Eq. 1.10 monotonicity.  At a
 // local extremum both edges take the zone average; otherwise the edge on the
