@@ -172,10 +172,30 @@ ppmlr_status ppmlr_kernel_times(ppmlr_ctx *ctx, double ms[3], long long launches
 ppmlr_status ppmlr_set_tile(ppmlr_ctx *ctx, int axis, int pencils);
 ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *pencils);
 
-/* Tile autotuner: for each axis, times `reps` sweeps of every tile shape that
- * fits one workgroup on a library-owned copy of the state (the caller's state
- * is not modified), keeps the fastest per axis and returns them in tiles[3]
- * (may be NULL).  The sweeps timed use the context's initial-guess mode
+/* Segments per pencil for sweeps along axis; 0 = automatic (one).  A sweep
+ * tile then holds `pencils` pencil segments of ceil(N / segments) interior
+ * zones (the last segment takes the rest) plus the 7 ghost zones on either
+ * side that the reconstruction, Riemann solve and remap of the sweep
+ * (Section II-B) reach: neighbouring segments overlap by those ghosts and
+ * each zone is computed by its own segment only, so the result does not
+ * depend on the segment count, bit for bit.  Shorter tiles trade recomputed
+ * ghost zones for fewer state planes per workgroup; the z sweep of a large
+ * grid, whose planes lie far apart in memory, gains most.  A segmented sweep
+ * reads zones that other workgroups update, so it writes a second state of
+ * the same size that the context allocates at its first use and keeps until
+ * ppmlr_destroy; sweeps alternate between the two, and a call that would
+ * end in the second state copies it back (ppmlr_advance with the z sweep
+ * segmented ends at home after an even number of steps).  EINVAL if a
+ * segment would be empty or shorter than 7 zones, or the current tile no
+ * longer fits one workgroup. */
+ppmlr_status ppmlr_set_segments(ppmlr_ctx *ctx, int axis, int segments);
+ppmlr_status ppmlr_get_segments(const ppmlr_ctx *ctx, int axis, int *segments);
+
+/* Tile autotuner: for each axis, times `reps` sweeps of every tile shape
+ * (pencils per workgroup, and segments per pencil from 1 to 8) that fits one
+ * workgroup on a library-owned copy of the state (the caller's state is not
+ * modified), keeps the fastest per axis (both are set on the context) and
+ * returns the pencils per workgroup in tiles[3] (may be NULL).  The sweeps timed use the context's initial-guess mode
  * (the harvest mode is timed as the plain one and records nothing); they add
  * to the counters.  Synchronises; allocates and frees one state-sized buffer. */
 ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, int tiles[3]);

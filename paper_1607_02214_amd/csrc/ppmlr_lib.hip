@@ -48,6 +48,9 @@ struct ppmlr_ctx {
     int partial_blocks = 0;
     long long step = 0;
     int tile[3] = {0, 0, 0};
+    int seg[3] = {0, 0, 0};                  // segments per pencil (0: one)
+    void *d_pong = nullptr;                  // second state for segmented sweeps
+    size_t pong_bytes = 0;
     int device = 0;
     std::string err;
     // profiling: event pairs around sweep launches
@@ -155,6 +158,22 @@ bool has_background(const ppmlr_ctx *c)
 // Threads needed for a tile of P pencils, rounded to whole waves.
 int block_threads(int P, int M) { return ((P * M + 63) / 64) * 64; }
 
+// Segments of a pencil of N zones cut into `nseg`: interior length of all but
+// the last (which is shorter or equal, and not empty); 0 if nseg is invalid.
+int seg_len(int N, int nseg)
+{
+    if (nseg < 1 || nseg > N) return 0;
+    const int L = (N + nseg - 1) / nseg;
+    return (nseg - 1) * L < N ? L : 0;
+}
+
+constexpr int kMaxSegments = 8;           // autotuner's search range
+
+int seg_count(const ppmlr_ctx *c, int axis) { return c->seg[axis] > 0 ? c->seg[axis] : 1; }
+
+// Zones of one tile's pencil segment (interior + ghosts).
+int tile_M(const ppmlr_ctx *c, int axis) { return seg_len(c->n[axis], seg_count(c, axis)) + 2 * kG; }
+
 // Automatic tile: the number of pencils per workgroup that wastes the fewest
 // lanes (padding to whole waves plus ghost zones), within the thread budget.
 // LDS stride of a sweep launch with `threads` lanes: the smallest of the
@@ -173,7 +192,7 @@ int stride_for(int threads, int elem)
 
 int auto_tile(const ppmlr_ctx *c, int axis, int elem)
 {
-    const int N = c->n[axis], M = N + 2 * kG;
+    const int N = seg_len(c->n[axis], seg_count(c, axis)), M = N + 2 * kG;
     const int cap = (elem == 8) ? 512 : 1024;
     const int nq = (axis == 0) ? c->n[1] : c->n[0];
     int best = 1;
@@ -195,10 +214,11 @@ int pick_tile(const ppmlr_ctx *c, int axis, int elem)
 }
 
 template <typename T>
-void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, double dt, const double *dt_dev, int P)
+void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, const T *in, T *u, int axis, double dt,
+               const double *dt_dev, int P, int nseg)
 {
     const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
-    const int N = c->n[axis], M = N + 2 * kG;
+    const int N = c->n[axis], L = seg_len(N, nseg), M = L + 2 * kG;
     const bool f64 = sizeof(T) == 8;
     auto tabs = [&](int ax, const T *&dx, const T *&xc, const T *&xf, const T *&dxi, const T *&xci) {
         const AxisTables &t = c->tab[ax];
@@ -213,9 +233,16 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     std::memset(&a, 0, sizeof(a));
     a.u = u;
     a.vol = (long long)nx * ny * nz;
-    for (int k = 0; k < 8; ++k) a.var[k] = u + (size_t)k * a.vol;
+    for (int k = 0; k < 8; ++k) {
+        a.vin[k] = in + (size_t)k * a.vol;
+        a.var[k] = u + (size_t)k * a.vol;
+    }
     a.N = N;
     a.M = M;
+    a.L = L;
+    a.nseg = nseg;
+    a.Mext = N + 2 * kG;
+    a.seg_fast = 1;
     a.P = P;
     a.S = P * M;
     int qax, rax;
@@ -266,7 +293,7 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, T *u, int axis, doubl
     // fetched bytes, so it is left off)
     a.group_q = a.tiles_q;
     a.nslots = ((a.tiles_q + a.group_q - 1) / a.group_q) * a.group_q * a.nr;
-    a.tiles_per_xcd = (a.nslots + 7) / 8;
+    a.tiles_per_xcd = (a.nslots * nseg + 7) / 8;
     a.mlp_frag = c->d_mlp_frag;
     a.mlp_theta = c->d_mlp_theta;
     a.gate_p = (T)c->gate_p;
@@ -341,14 +368,15 @@ ppmlr_status launch_axis(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t
 }
 
 template <typename T>
-ppmlr_status sweep_typed(ppmlr_ctx *c, T *u, hipStream_t st, double dt, const double *dt_dev, int axis, bool fuse)
+ppmlr_status sweep_typed(ppmlr_ctx *c, const T *in, T *u, hipStream_t st, double dt, const double *dt_dev, int axis,
+                         bool fuse)
 {
     const int P = pick_tile(c, axis, (int)sizeof(T));
-    const int M = c->n[axis] + 2 * kG;
+    const int M = tile_M(c, axis);
     if (block_threads(P, M) > 1024 || (size_t)(kSlotsA + kSlotsB) * P * M * sizeof(T) > 160 * 1024)
         return fail(c, PPMLR_EINVAL, "tile does not fit one workgroup");
     ppmlr::SweepArgs<T> a;
-    fill_args(c, a, u, axis, dt, dt_dev, P);
+    fill_args(c, a, in, u, axis, dt, dt_dev, P, seg_count(c, axis));
     const bool stats = c->opt.collect_stats != 0;
     if (axis == 0) return launch_axis<0, T>(c, a, st, stats, fuse);
     if (axis == 1) return launch_axis<1, T>(c, a, st, stats, fuse);
@@ -378,9 +406,57 @@ hipEvent_t pooled_event(ppmlr_ctx *c)
     return e;
 }
 
-ppmlr_status do_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, const double *dt_dev, int axis, bool fuse)
+// Where the state of a sequence of sweeps is: the caller's buffer (home) or
+// the context's second state.  Whole-pencil sweeps update in place (each
+// workgroup reads and writes its own pencils only).  A segmented sweep reads
+// its ghost zones from neighbouring segments that other workgroups update,
+// so it writes the other buffer; a whole-pencil sweep that reads the second
+// state writes home, so the pair of adjacent segmented sweeps of a split
+// step pair ends at home.
+struct Flow {
+    void *home, *cur;
+};
+
+size_t state_bytes(const ppmlr_ctx *c, const ppmlr_state *s)
+{
+    return (size_t)8 * c->n[0] * c->n[1] * c->n[2] * (s->dtype == PPMLR_F64 ? 8 : 4);
+}
+
+ppmlr_status ensure_pong(ppmlr_ctx *c, size_t bytes)
+{
+    if (c->pong_bytes >= bytes) return PPMLR_OK;
+    if (c->d_pong) {
+        ppmlr_status e = hip_check(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (e) return e;
+        (void)hipFree(c->d_pong);
+        c->d_pong = nullptr;
+        c->pong_bytes = 0;
+    }
+    ppmlr_status e = hip_check(c, hipMalloc(&c->d_pong, bytes), "hipMalloc");
+    if (!e) c->pong_bytes = bytes;
+    return e;
+}
+
+// Bring the state home after a sequence of sweeps.
+ppmlr_status finish_flow(ppmlr_ctx *c, const ppmlr_state *s, Flow &f)
+{
+    if (f.cur == f.home) return PPMLR_OK;
+    ppmlr_status e = hip_check(c, hipMemcpyAsync(f.home, f.cur, state_bytes(c, s), hipMemcpyDeviceToDevice,
+                                                 (hipStream_t)s->stream), "hipMemcpyAsync");
+    f.cur = f.home;
+    return e;
+}
+
+ppmlr_status do_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, const double *dt_dev, int axis, bool fuse,
+                      Flow &f)
 {
     hipStream_t st = (hipStream_t)s->stream;
+    void *out = f.home;
+    if (seg_count(c, axis) > 1) {
+        ppmlr_status e = ensure_pong(c, state_bytes(c, s));
+        if (e) return e;
+        out = (f.cur == f.home) ? c->d_pong : f.home;
+    }
     ppmlr_ctx::Mark mk{nullptr, nullptr, axis};
     if (c->profiling) {
         mk.start = pooled_event(c);
@@ -389,8 +465,10 @@ ppmlr_status do_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, const doubl
         ppmlr_status e = hip_check(c, hipEventRecord(mk.start, st), "hipEventRecord");
         if (e) return e;
     }
-    ppmlr_status r = (s->dtype == PPMLR_F64) ? sweep_typed<double>(c, (double *)s->u, st, dt, dt_dev, axis, fuse)
-                                             : sweep_typed<float>(c, (float *)s->u, st, dt, dt_dev, axis, fuse);
+    ppmlr_status r = (s->dtype == PPMLR_F64)
+                         ? sweep_typed<double>(c, (const double *)f.cur, (double *)out, st, dt, dt_dev, axis, fuse)
+                         : sweep_typed<float>(c, (const float *)f.cur, (float *)out, st, dt, dt_dev, axis, fuse);
+    if (!r) f.cur = out;
     if (c->profiling) {
         ppmlr_status e = hip_check(c, hipEventRecord(mk.stop, st), "hipEventRecord");
         if (e) return e;
@@ -677,6 +755,7 @@ void ppmlr_destroy(ppmlr_ctx *c)
     }
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     if (c->d_mlp_frag) (void)hipFree(c->d_mlp_frag);
+    if (c->d_pong) (void)hipFree(c->d_pong);
     if (c->d_mlp_theta) (void)hipFree(c->d_mlp_theta);
     free_tables(c);
     delete c;
@@ -761,7 +840,10 @@ ppmlr_status ppmlr_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, int axis
     if (e) return e;
     if (axis < 0 || axis > 2) return fail(c, PPMLR_EINVAL, "axis must be 0, 1 or 2");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, PPMLR_EINVAL, "dt must be positive and finite");
-    return do_sweep(c, s, dt, nullptr, axis, false);
+    Flow f{s->u, s->u};
+    e = do_sweep(c, s, dt, nullptr, axis, false, f);
+    if (e) return e;
+    return finish_flow(c, s, f);
 }
 
 ppmlr_status ppmlr_step(ppmlr_ctx *c, const ppmlr_state *s, double dt)
@@ -777,12 +859,13 @@ ppmlr_status ppmlr_step(ppmlr_ctx *c, const ppmlr_state *s, double dt)
     }
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     const int *ord = (c->step % 2 == 0) ? even : odd;
+    Flow f{s->u, s->u};
     for (int k = 0; k < 3; ++k) {
-        e = do_sweep(c, s, dt, nullptr, ord[k], false);
+        e = do_sweep(c, s, dt, nullptr, ord[k], false, f);
         if (e) return e;
     }
     c->step++;
-    return PPMLR_OK;
+    return finish_flow(c, s, f);
 }
 
 ppmlr_status ppmlr_set_step_index(ppmlr_ctx *c, long long step)
@@ -828,15 +911,18 @@ ppmlr_status ppmlr_advance(ppmlr_ctx *c, const ppmlr_state *s, int nsteps, doubl
     e = cfl_launch(c, s);   // signal-speed maximum of the current state
     if (e) return e;
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    Flow f{s->u, s->u};
     for (int n = 0; n < nsteps; ++n) {
         hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(1), 0, st, c->d_cflmax, c->d_dt, c->d_time, cfl);
         const int *ord = (c->step % 2 == 0) ? even : odd;
         for (int k = 0; k < 3; ++k) {
-            e = do_sweep(c, s, 0.0, c->d_dt, ord[k], k == 2);
+            e = do_sweep(c, s, 0.0, c->d_dt, ord[k], k == 2, f);
             if (e) return e;
         }
         c->step++;
     }
+    e = finish_flow(c, s, f);
+    if (e) return e;
     return hip_check(c, hipGetLastError(), "advance");
 }
 
@@ -913,12 +999,31 @@ ppmlr_status ppmlr_set_tile(ppmlr_ctx *c, int axis, int pencils)
 {
     if (!c || axis < 0 || axis > 2 || pencils < 0) return PPMLR_EINVAL;
     if (pencils > 0) {
-        int M = c->n[axis] + 2 * kG;
+        int M = tile_M(c, axis);
         if (block_threads(pencils, M) > 1024) return fail(c, PPMLR_EINVAL, "tile exceeds 1024 threads");
         if ((size_t)(kSlotsA + kSlotsB) * pencils * M * 4 > 160 * 1024)
             return fail(c, PPMLR_EINVAL, "tile exceeds the LDS budget");
     }
     c->tile[axis] = pencils;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_segments(ppmlr_ctx *c, int axis, int segments)
+{
+    if (!c || axis < 0 || axis > 2 || segments < 0) return PPMLR_EINVAL;
+    const int L = seg_len(c->n[axis], segments > 0 ? segments : 1);
+    if (L == 0) return fail(c, PPMLR_EINVAL, "segment count leaves a segment empty");
+    if (segments > 1 && L < kG) return fail(c, PPMLR_EINVAL, "segments shorter than the ghost width");
+    if (c->tile[axis] > 0 && block_threads(c->tile[axis], L + 2 * kG) > 1024)
+        return fail(c, PPMLR_EINVAL, "tile exceeds 1024 threads");
+    c->seg[axis] = segments;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_get_segments(const ppmlr_ctx *c, int axis, int *segments)
+{
+    if (!c || axis < 0 || axis > 2 || !segments) return PPMLR_EINVAL;
+    *segments = seg_count(c, axis);
     return PPMLR_OK;
 }
 
@@ -946,25 +1051,33 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
     ppmlr_state tmp = *s;
     tmp.u = scratch;
     for (int axis = 0; axis < 3 && !e; ++axis) {
-        const int M = c->n[axis] + 2 * kG;
-        int best = 1;
+        int best = 1, best_seg = 1;
         float best_ms = 1e30f;
-        for (int P = 1; P <= 32 && !e; ++P) {
-            const int thr = block_threads(P, M);
-            if (thr > 1024) break;
-            if (stride_for(thr, (int)elem) < 0) continue;
-            c->tile[axis] = P;
-            e = hip_check(c, hipMemcpyAsync(scratch, s->u, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-            if (!e) e = do_sweep(c, &tmp, dt, nullptr, axis, false);   // warm-up
-            if (!e) e = hip_check(c, hipEventRecord(t0, st), "hipEventRecord");
-            for (int r = 0; r < reps && !e; ++r) e = do_sweep(c, &tmp, dt, nullptr, axis, false);
-            if (!e) e = hip_check(c, hipEventRecord(t1, st), "hipEventRecord");
-            if (!e) e = hip_check(c, hipEventSynchronize(t1), "hipEventSynchronize");
-            float ms = 0.0f;
-            if (!e) e = hip_check(c, hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
-            if (!e && ms < best_ms) { best_ms = ms; best = P; }
+        for (int nseg = 1; nseg <= kMaxSegments && !e; ++nseg) {
+            const int L = seg_len(c->n[axis], nseg);
+            if (L == 0) continue;
+            if (L < kG) break;
+            const int M = L + 2 * kG;
+            c->seg[axis] = nseg;
+            for (int P = 1; P <= 32 && !e; ++P) {
+                const int thr = block_threads(P, M);
+                if (thr > 1024) break;
+                if (stride_for(thr, (int)elem) < 0) continue;
+                c->tile[axis] = P;
+                e = hip_check(c, hipMemcpyAsync(scratch, s->u, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+                Flow f{scratch, scratch};
+                if (!e) e = do_sweep(c, &tmp, dt, nullptr, axis, false, f);   // warm-up
+                if (!e) e = hip_check(c, hipEventRecord(t0, st), "hipEventRecord");
+                for (int r = 0; r < reps && !e; ++r) e = do_sweep(c, &tmp, dt, nullptr, axis, false, f);
+                if (!e) e = hip_check(c, hipEventRecord(t1, st), "hipEventRecord");
+                if (!e) e = hip_check(c, hipEventSynchronize(t1), "hipEventSynchronize");
+                float ms = 0.0f;
+                if (!e) e = hip_check(c, hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+                if (!e && ms < best_ms) { best_ms = ms; best = P; best_seg = nseg; }
+            }
         }
         c->tile[axis] = best;
+        c->seg[axis] = best_seg;
         if (tiles) tiles[axis] = best;
     }
     c->profiling = prof;
@@ -1015,7 +1128,7 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
             const int nq = (ax == 0) ? c->n[1] : c->n[0];
             const int P = std::max(1, std::min(block / M, nq));
             ppmlr::SweepArgs<T> &a = desc[(size_t)ax * n + m];
-            fill_args(c, a, (T *)states[m]->u, ax, 0.0, c->d_dt, P);
+            fill_args(c, a, (const T *)states[m]->u, (T *)states[m]->u, ax, 0.0, c->d_dt, P, 1);
             mo[(size_t)ax * (n + 1) + m] = (int)off;
             off += a.ntiles;
         }

@@ -84,17 +84,21 @@ template <typename T>
 struct SweepArgs {
     T *u;                       // state, SoA [8][nz][ny][nx]
     long long vol;              // zones per variable
-    int N, M;                   // zones along the pencil, N + 2G
+    int N, M;                   // zones along the pencil; zones of one tile's segment, L + 2G
+    int L, nseg;                // interior zones per segment (the last may be shorter), segments per pencil
+    int Mext;                   // N + 2G: extent of the geometry tables along the pencil
     int P;                      // pencils per workgroup
     int S;                      // LDS slots = P * M
     long long stride_n, stride_q, stride_r;   // element strides
     float inv_div;              // 1 / M (x sweep) or 1 / P (y, z): lane -> (pencil, zone)
-    T *var[8];                  // u + k * vol: base of each conserved variable
+    const T *vin[8];            // base of each conserved variable of the input state
+    T *var[8];                  // ... and of the output state (the same when whole pencils are swept in place)
     int nq, nr;                 // pencils along q (memory-fastest transverse) and r
-    int tiles_q, ntiles, tiles_per_xcd;
+    int tiles_q, ntiles, tiles_per_xcd;   // ntiles: tiles of one segment band (tiles_q * nr)
     int group_q;                // tiles along q taken together before stepping r (>= 1)
-    int nslots;                 // enumerated tile slots: ceil(tiles_q / group_q) * group_q * nr
-    const T *dx, *xc, *xf;      // sweep axis: extended widths [M], centres [M], faces [M+1]
+    int nslots;                 // tile slots of one segment band: ceil(tiles_q / group_q) * group_q * nr
+    int seg_fast;               // 1: consecutive tiles are the segments of one pencil group; 0: bands in turn
+    const T *dx, *xc, *xf;      // sweep axis: extended widths [Mext], centres [Mext], faces [Mext+1]
     const T *xc_q, *xc_r;       // transverse centres (interior zones)
     const T *dx_q, *dx_r;       // transverse widths (interior zones)
     int bc_lo, bc_hi;
@@ -297,9 +301,6 @@ __device__ inline void wave_hist(unsigned int *s_hist, bool counted, int bin)
     }
 }
 
-// One tile (P whole pencils) of a sweep, executed by one workgroup.  tq, r:
-// tile position (q tiles of P pencils, r the slow transverse index); dt: the
-// time step; cfl_max: target of the fused signal-speed maximum (FUSE_CFL);
 // Inputs of the learned guess for one face (see the Riemann block of
 // sweep_tile): sides s = (rho, u, v_t1, v_t2, B_t1, B_t2, P), normalised by
 // the pair means.  Returns whether the face is selected (strong pressure or
@@ -329,7 +330,18 @@ __device__ inline bool guess_features(const T *L, const T *R, T gate_p, T gate_u
     return tabs(R[6] - L[6]) > gate_p * tmin(L[6], R[6]) || tabs(R[1] - L[1]) > gate_u * cbar;
 }
 
-// stat_slot: which copy of the counters this workgroup adds to.
+// One tile of a sweep, executed by one workgroup: P pencils, each cut to
+// segment `seg` (interior zones seg*L .. seg*L + L - 1 with G zones on either
+// side; one segment = the whole pencil).  A zone's result depends on the
+// zones within G of it only, so segments give the whole-pencil result
+// bit for bit; neighbour reads are clamped at the ends of the pencil's
+// extended range, as for a whole pencil.  tq, r: tile position (q tiles of P
+// pencils, r the slow transverse index).  The state is read through a.vin
+// and written through a.var: the same buffer for whole pencils, different
+// buffers for segments (a segment's ghost zones are other segments' interior
+// zones).  dt: the time step; cfl_max: target
+// of the fused signal-speed maximum (FUSE_CFL); stat_slot: which copy of the
+// counters this workgroup adds to.
 // SM: LDS stride per stored value (a power of two >= P*M, so that every LDS
 // access uses an immediate offset), or 0 for a runtime stride P*M.
 // GUESS: initial guess of the normal-pair Newton iteration: the plain linear
@@ -337,7 +349,7 @@ __device__ inline bool guess_features(const T *L, const T *R, T gate_p, T gate_u
 // the selected faces' states and solutions recorded for training.  s_guess:
 // one LDS counter (learned mode).
 template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain>
-__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, const int r, const T dt,
+__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, const int r, const int seg, const T dt,
                                            unsigned long long *cfl_max, const int stat_slot,
                                            unsigned char *smem_raw, double *s_red, unsigned int *s_stat,
                                            unsigned int *s_guess = nullptr)
@@ -363,14 +375,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     else { i = qd; p = tid - i * P; }                     // pencils adjacent (coalesced)
     const int d = (AX == 0) ? 1 : P;                      // slot offset of zone i+1
     const int q = q0 + p;
-    const bool pen = slot_ok && q < a.nq;
-    const int g = i - kG;                                 // zone index along the pencil
-    const bool interior = pen && g >= 0 && g < N;
+    const int g0 = seg * a.L;                             // first interior zone of the segment
+    const int ie = g0 + i;                                // index into the extended tables
+    const int Mext = a.Mext;
+    const bool pen = slot_ok && q < a.nq && ie < Mext;
+    const int g = ie - kG;                                // zone index along the pencil
+    const int gend = min(g0 + a.L, N);                    // end of the segment's interior
+    const bool interior = pen && g >= g0 && g < gend;
     const int tsafe = slot_ok ? tid : Suse - 1;           // padding lanes read a valid slot
     auto nb = [&](int k) -> int {                         // slot of zone i+k (clamped)
         int ii = i + k;
-        return (ii >= 0 && ii < M && slot_ok) ? tid + k * d : tsafe;
+        return (ii >= 0 && ii < M && ie + k >= 0 && ie + k < Mext && slot_ok) ? tid + k * d : tsafe;
     };
+    // faces owned by this segment (counted and recorded once per pencil):
+    // -1/2 .. N-1/2 over all segments
+    const int own_lo = seg == 0 ? -1 : g0;
     const T gam = a.gamma;
 
     // transverse coordinates of the pencil
@@ -386,7 +405,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     const unsigned int base = (unsigned int)(qq * (int)a.stride_q + r * (int)a.stride_r);
 
     // ------------------------------------------------------------ R1
-    const int ic = i < M ? i : M - 1;
+    const int ic = ie < Mext ? ie : Mext - 1;
     const T dxi = elem(a.dx, ic);
     const T xci = elem(a.xc, ic);
     const T xfr = elem(a.xf, ic + 1);
@@ -412,14 +431,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     constexpr int kn = AX, k1 = (AX + 1) % 3, k2 = (AX + 2) % 3;
     if (pen && !inflow_zone) {
         const unsigned int o = base + (unsigned int)(src * (int)a.stride_n);
-        Q[0] = elem(a.var[0], o);
-        Q[1] = elem(a.var[1 + kn], o);
-        Q[2] = elem(a.var[1 + k1], o);
-        Q[3] = elem(a.var[1 + k2], o);
-        Q[4] = elem(a.var[4 + kn], o);
-        Q[5] = elem(a.var[4 + k1], o);
-        Q[6] = elem(a.var[4 + k2], o);
-        Q[7] = elem(a.var[7], o);
+        Q[0] = elem(a.vin[0], o);
+        Q[1] = elem(a.vin[1 + kn], o);
+        Q[2] = elem(a.vin[1 + k1], o);
+        Q[3] = elem(a.vin[1 + k2], o);
+        Q[4] = elem(a.vin[4 + kn], o);
+        Q[5] = elem(a.vin[4 + k1], o);
+        Q[6] = elem(a.vin[4 + k2], o);
+        Q[7] = elem(a.vin[7], o);
     } else if (pen) {
         // inflow ghost: primitive inflow state with B' = B_in - B_d(centre)
         T vn, v1, v2, Bn, B1, B2;
@@ -661,7 +680,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
                 dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
             }
         }
-        if (STATS) wave_add(&s_stat[35], lg_gate);
+        if (STATS) wave_add(&s_stat[35], lg_gate && g >= own_lo && g < gend);
         __syncthreads();
         const int nf = min((int)s_guess[0], kCap);
         for (int b0 = (tid >> 6) * 64; b0 < nf; b0 += (int)(blockDim.x >> 6) * 64)
@@ -703,7 +722,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         if (GUESS == kGuessHarvest) {
             const T Ls[7] = {LrN, Lu, Lv1, Lv2, LT1, LT2, PL};
             const T Rs[7] = {RrN, Ru, Rv1, Rv2, RT1, RT2, PR};
-            gate = face_ok && guess_features(Ls, Rs, a.gate_p, a.gate_u, feat, Pbar, cbar);
+            gate = face_ok && g >= own_lo && g < gend && guess_features(Ls, Rs, a.gate_p, a.gate_u, feat, Pbar, cbar);
             if (STATS) wave_add(&s_stat[35], gate);
         }
         if (GUESS == kGuessLearned) {
@@ -715,7 +734,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
                     used = true;
                 }
             }
-            if (STATS) wave_add(&s_stat[36], lg_gate && !used);
+            if (STATS) wave_add(&s_stat[36], lg_gate && !used && g >= own_lo && g < gend);
         }
         int it = 0;
         bool conv = true;
@@ -774,9 +793,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             }
         }
         if (STATS) {
-            // faces -1/2 .. N-1/2 of the pencil: iteration histogram and
-            // non-converged count; zone counters of R1 (after the first barrier)
-            const bool counted = face_ok && g >= -1 && g <= N - 1;
+            // owned faces: iteration histogram and non-converged count; zone
+            // counters of R1 (after the first barrier)
+            const bool counted = face_ok && g >= own_lo && g < gend;
             wave_hist(s_stat, counted, it < 31 ? it : 31);
             wave_add(&s_stat[33], counted && !conv);
             wave_add(&s_stat[32], cnt_floor);
@@ -898,7 +917,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         T nbn = bn, nb1 = nw[4], nb2 = nw[5];
         if (a.janhunen) {
             // -v div B' source, split: n-derivative of B'_n, pre-sweep velocity
-            const T xm = elem(a.xc, i - 1), xp = elem(a.xc, i + 1);
+            const T xm = elem(a.xc, ie - 1), xp = elem(a.xc, ie + 1);
             const T divn = (bnp - bnm) * Ar<T>::rcp(xp - xm);
             nbn -= dt * un * divn;
             nb1 -= dt * v1 * divn;
@@ -1008,10 +1027,14 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     // of group_q tiles adjacent along q (sharing cache lines) run together and
     // successive groups step along r, so that the lines in flight spread over
     // many L2 sets when the pencil stride is a large power-of-two multiple
-    // (z sweeps).
+    // (z sweeps).  Segments of a pencil are either adjacent in this order
+    // (seg_fast) or in successive bands of the whole grid.
     const int b = blockIdx.x;
-    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
-    if (tile >= a.nslots) return;
+    const int slot = (b & 7) * a.tiles_per_xcd + (b >> 3);
+    if (slot >= a.nslots * a.nseg) return;
+    int seg, tile;
+    if (a.seg_fast) { seg = slot % a.nseg; tile = slot / a.nseg; }
+    else { seg = slot / a.nslots; tile = slot - seg * a.nslots; }
     const int gq = a.group_q;
     const int gsz = gq * a.nr;
     const int xg = tile / gsz;
@@ -1020,7 +1043,7 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     const int tq = xg * gq + (rem - r * gq);
     if (tq >= a.tiles_q) return;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat,
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, seg, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat,
                                                   s_guess);
 }
 
@@ -1032,7 +1055,7 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
 // same XCD-aware order as the single-run kernel.  Each member's geometry, dt
 // pointer, signal-speed slot and counters are in its own descriptor, so a
 // member's arithmetic is exactly that of a single-run sweep with the same
-// tiles.  Successive sweeps are ordered by the launch boundaries: no
+// tiles (whole pencils: members have one segment).  Successive sweeps are ordered by the launch boundaries: no
 // workgroup waits on another.
 template <typename T>
 struct EnsembleSweepArgs {
@@ -1060,7 +1083,7 @@ __global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepA
     const int tq = t % a.tiles_q;
     const int r = t / a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, 0, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
 }
 
 }  // namespace ppmlr
