@@ -241,6 +241,9 @@ def main():
     ap.add_argument("--harvest-cap", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--ensemble-steps", type=int, default=50)
+    ap.add_argument("--tiles", type=str, default=None,
+                    help="pencils per tile x,y,z for the FP32 run (with --segments: no autotuning)")
+    ap.add_argument("--segments", type=str, default=None, help="segments per pencil x,y,z for the FP32 run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -268,11 +271,18 @@ def main():
         ctx.set_inner(setup.inner_rho, setup.inner_p)
         return ctx
 
-    def run(dtype, steps, warmup, profile=True):
+    def run(dtype, steps, warmup, profile=True, shape=None):
         ctx = make_ctx()
         u = torch.from_numpy(setup.U).to(device="cuda", dtype=dtype).contiguous()
-        tiles = ctx.autotune(u, reps=3)          # tile search (outside the timed region)
-        print(f"[bench] autotuned tiles {tiles}", file=sys.stderr, flush=True)
+        if shape is None:
+            ctx.autotune(u, reps=3)              # tile search (outside the timed region)
+        else:
+            for a in range(3):
+                ctx.set_tile(a, 1)
+                ctx.set_segments(a, shape[1][a])
+                ctx.set_tile(a, shape[0][a])
+        print(f"[bench] tiles {[ctx.get_tile(a) for a in range(3)]} segments {[ctx.get_segments(a) for a in range(3)]}"
+              f"{'' if shape is None else ' (given)'}", file=sys.stderr, flush=True)
         ctx.advance(u, warmup, args.cfl)
         torch.cuda.synchronize()
         ctx.reset_stats()
@@ -302,7 +312,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print(f"[bench] fp32: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
-    ctx, u, ms, wall, kms, kn, status, st, finite = run(torch.float32, args.steps, args.warmup)
+    shape = None
+    if args.tiles or args.segments:
+        if not (args.tiles and args.segments):
+            raise SystemExit("--tiles and --segments go together")
+        shape = ([int(x) for x in args.tiles.split(",")], [int(x) for x in args.segments.split(",")])
+    ctx, u, ms, wall, kms, kn, status, st, finite = run(torch.float32, args.steps, args.warmup, shape=shape)
     value = zones * args.steps / (ms / 1000.0)
     avg = [kms[a] / kn[a] if kn[a] else 0.0 for a in range(3)]
     dom = int(np.argmax(avg))
@@ -344,6 +359,8 @@ def main():
             "grid": [nx, ny, nz],
             "cfl": args.cfl,
             "tiles": [ctx.get_tile(a, ppmlr.F32) for a in range(3)],
+            "segments": [ctx.get_segments(a) for a in range(3)],
+            "tile_search": "autotuned" if shape is None else "given",
         },
         "roofline": roofline,
         "health": {"status": status, "finite": finite, "floor_hits": st["floor_hits"],
