@@ -179,7 +179,7 @@ def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
 
 def ensemble_leg(args):
     """The 32-member batched ensemble (uneven cubic grids 96^3..160^3, seeded
-    solar-wind inputs), FP32, autotuned workgroup size, timed over
+    solar-wind inputs), FP32, autotuned workgroup size and segment length, timed over
     args.ensemble_steps steps after 2 warm-up steps."""
     import torch
     from paper_1607_02214_amd import inputs as I
@@ -220,6 +220,8 @@ def ensemble_leg(args):
         "steps": args.ensemble_steps,
         "ms_per_step": ms / args.ensemble_steps,
         "block": block,
+        "segments_of_largest_member": [ctxs[max(range(len(spec)), key=lambda k: spec[k]["N"])].get_segments(a)
+                                       for a in range(3)],
         "status": sorted(set(status)),
         "finite": finite,
         "simulated_time_range": [min(times), max(times)],

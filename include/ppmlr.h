@@ -214,17 +214,24 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, 
  * may be in use elsewhere meanwhile.
  * block: workgroup size 256, 512 or 1024 (every pencil + 14 ghosts must fit;
  * 1024 is FP32 only), or 0 for the value chosen by ppmlr_ensemble_autotune
- * (512 if it never ran); pencils per workgroup per member and axis are the
- * most that fit the workgroup.  per_member (may be NULL) receives each
+ * (512 if it never ran); each member's pencils are cut into the segments
+ * its context is set to (ppmlr_set_segments), and pencils per workgroup per
+ * member and axis are the most that fit the workgroup.  A member with
+ * segments alternates between its state and its context's second state
+ * (allocated at first use) every sweep, and is copied back after an odd
+ * number of sweeps.  per_member (may be NULL) receives each
  * member's ppmlr_status_check result.  Synchronises; allocates and frees its
  * work tables. */
 ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
                                 double cfl, int block, ppmlr_status *per_member);
 
 /* Ensemble tile autotuner: times `reps` ensemble steps for each feasible
- * workgroup size on library-owned copies of the states (the callers' states,
- * step counters and times are left unchanged), stores the fastest for
- * ensemble calls with block = 0 and returns it in *block (may be NULL). */
+ * workgroup size (256, 512, 1024) and target segment length (whole pencils,
+ * or segments of about 96, 64, 48 or 32 interior zones) on library-owned
+ * copies of the states (the callers' states, step counters and times are
+ * left unchanged), stores the fastest workgroup size for ensemble calls with
+ * block = 0, returns it in *block (may be NULL), and sets every member
+ * context's segments per axis to the fastest length's. */
 ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int reps,
                                      double cfl, int *block);
 

@@ -1114,9 +1114,23 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
 {
     ppmlr_ctx *c0 = ctxs[0];
     hipStream_t st = (hipStream_t)states[0]->stream;
-    // per axis and member: pencils per workgroup = as many as fit the block;
-    // dt from the member's device dt, signal speeds into its own slot
-    std::vector<ppmlr::SweepArgs<T>> desc((size_t)3 * n);
+    // Members whose pencils are cut into segments (their contexts' setting)
+    // alternate every sweep between their state and their context's second
+    // state: sweep j of this call reads the first when j is even.  The other
+    // members sweep in place.
+    std::vector<char> pp(n, 0);
+    for (int m = 0; m < n; ++m) {
+        for (int ax = 0; ax < 3; ++ax)
+            if (seg_count(ctxs[m], ax) > 1) pp[m] = 1;
+        if (pp[m]) {
+            ppmlr_status e = ensure_pong(ctxs[m], state_bytes(ctxs[m], states[m]));
+            if (e) return e;
+        }
+    }
+    // per axis, sweep parity and member: pencils per workgroup = as many as
+    // fit the block; dt from the member's device dt, signal speeds into its
+    // own slot
+    std::vector<ppmlr::SweepArgs<T>> desc((size_t)6 * n);
     std::vector<int> mo((size_t)3 * (n + 1));
     bool stats = false;
     for (int ax = 0; ax < 3; ++ax) {
@@ -1124,13 +1138,18 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         for (int m = 0; m < n; ++m) {
             ppmlr_ctx *c = ctxs[m];
             if (c->opt.collect_stats) stats = true;
-            const int M = c->n[ax] + 2 * kG;
+            const int nseg = seg_count(c, ax);
+            const int M = tile_M(c, ax);
             const int nq = (ax == 0) ? c->n[1] : c->n[0];
             const int P = std::max(1, std::min(block / M, nq));
-            ppmlr::SweepArgs<T> &a = desc[(size_t)ax * n + m];
-            fill_args(c, a, (const T *)states[m]->u, (T *)states[m]->u, ax, 0.0, c->d_dt, P, 1);
+            T *home = (T *)states[m]->u, *pong = (T *)c->d_pong;
+            for (int par = 0; par < 2; ++par) {
+                const T *in = (pp[m] && par) ? pong : home;
+                T *out = pp[m] ? (par ? home : pong) : home;
+                fill_args(c, desc[((size_t)ax * 2 + par) * n + m], in, out, ax, 0.0, c->d_dt, P, nseg);
+            }
             mo[(size_t)ax * (n + 1) + m] = (int)off;
-            off += a.ntiles;
+            off += (long long)desc[(size_t)ax * 2 * n + m].ntiles * nseg;
         }
         if (off > (long long)INT_MAX / 2) return fail(c0, PPMLR_EINVAL, "ensemble too large for one launch");
         mo[(size_t)ax * (n + 1) + n] = (int)off;
@@ -1166,6 +1185,7 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
     for (int m = 0; m < n && !err; ++m) err = cfl_launch(ctxs[m], states[m]);
     const size_t lds = (size_t)(kSlotsA + kSlotsB) * block * sizeof(T);
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    long long j = 0;                                       // sweeps enqueued by this call
     for (int s = 0; s < steps && !err; ++s) {
         hipLaunchKernelGGL(ens_dt_kernel, dim3((n + 63) / 64), dim3(64), 0, st, (unsigned long long *const *)d_ptr,
                            (double *const *)(d_ptr + n), (double *const *)(d_ptr + 2 * (size_t)n), n, cfl);
@@ -1173,7 +1193,7 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         for (int k = 0; k < 3 && !err; ++k) {
             const int ax = ord[k];
             ppmlr::EnsembleSweepArgs<T> e;
-            e.desc = d_desc + (size_t)ax * n;
+            e.desc = d_desc + ((size_t)ax * 2 + (size_t)(j & 1)) * n;
             e.mo = d_mo + (size_t)ax * (n + 1);
             e.members = n;
             e.total = mo[(size_t)ax * (n + 1) + n];
@@ -1203,8 +1223,15 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
 #undef PPMLR_ENS
 #undef PPMLR_ENS3
             if (!err) err = hip_check(c0, hipGetLastError(), "ensemble sweep launch");
+            ++j;
         }
     }
+    // after an odd number of sweeps the alternating members are in their
+    // second state
+    for (int m = 0; m < n && !err && (j & 1); ++m)
+        if (pp[m])
+            err = hip_check(c0, hipMemcpyAsync(states[m]->u, ctxs[m]->d_pong, state_bytes(ctxs[m], states[m]),
+                                               hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
     // the device tables are freed once the launches that read them are done
     (void)hipStreamSynchronize(st);
     for (void *p : allocs) (void)hipFree(p);
@@ -1280,24 +1307,37 @@ ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *
         if (!e) e = hip_check(ctxs[m], hipMemcpy(&time0[m], ctxs[m]->d_time, sizeof(double), hipMemcpyDeviceToHost),
                               "hipMemcpy");
     }
-    int best = 0;
+    int best = 0, best_len = 0;
     float best_ms = 1e30f;
     const int cands[3] = {256, 512, 1024};
+    // target interior zones per segment (0: whole pencils)
+    const int lens[5] = {0, 96, 64, 48, 32};
+    auto set_lengths = [&](int len) {
+        for (int m = 0; m < n; ++m)
+            for (int ax = 0; ax < 3; ++ax) {
+                const int N = ctxs[m]->n[ax];
+                int k = len > 0 ? (N + len - 1) / len : 1;
+                while (k > 1 && (seg_len(N, k) == 0 || seg_len(N, k) < kG)) --k;
+                ctxs[m]->seg[ax] = k;
+            }
+    };
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (!e) e = hip_check(ctxs[0], hipEventCreate(&t0), "hipEventCreate");
     if (!e) e = hip_check(ctxs[0], hipEventCreate(&t1), "hipEventCreate");
-    for (int ci = 0; ci < 3 && !e; ++ci) {
-        const int B = cands[ci];
+    for (int cand = 0; cand < 15 && !e; ++cand) {
+        const int B = cands[cand / 5], len = lens[cand % 5];
         if (ensemble_check(ctxs, tptr.data(), n, reps, cfl, B) != PPMLR_OK) continue;
+        set_lengths(len);
         e = hip_check(ctxs[0], hipEventRecord(t0, st), "hipEventRecord");
         if (!e) e = ppmlr_ensemble_run(ctxs, tptr.data(), n, reps, cfl, B, nullptr);
         if (!e) e = hip_check(ctxs[0], hipEventRecord(t1, st), "hipEventRecord");
         if (!e) e = hip_check(ctxs[0], hipEventSynchronize(t1), "hipEventSynchronize");
         float ms = 0.0f;
         if (!e) e = hip_check(ctxs[0], hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
-        if (!e && ms < best_ms) { best_ms = ms; best = B; }
+        if (!e && ms < best_ms) { best_ms = ms; best = B; best_len = len; }
         for (int m = 0; m < n; ++m) ctxs[m]->step = step0[m];
     }
+    set_lengths(best_len);
     for (int m = 0; m < n; ++m) {
         ctxs[m]->step = step0[m];
         ctxs[m]->opt.collect_stats = stat0[m];

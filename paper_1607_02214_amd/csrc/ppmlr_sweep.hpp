@@ -1055,7 +1055,8 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
 // same XCD-aware order as the single-run kernel.  Each member's geometry, dt
 // pointer, signal-speed slot and counters are in its own descriptor, so a
 // member's arithmetic is exactly that of a single-run sweep with the same
-// tiles (whole pencils: members have one segment).  Successive sweeps are ordered by the launch boundaries: no
+// tiles (and segments: a segmented member reads one state and writes the
+// other, as a single run does).  Successive sweeps are ordered by the launch boundaries: no
 // workgroup waits on another.
 template <typename T>
 struct EnsembleSweepArgs {
@@ -1080,10 +1081,12 @@ __global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepA
     }
     const SweepArgs<T> &a = e.desc[lo];
     const int t = j - e.mo[lo];
-    const int tq = t % a.tiles_q;
-    const int r = t / a.tiles_q;
+    const int seg = t % a.nseg;                   // segments of a pencil group adjacent
+    const int tt = t / a.nseg;
+    const int tq = tt % a.tiles_q;
+    const int r = tt / a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, 0, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, seg, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
 }
 
 }  // namespace ppmlr

@@ -376,8 +376,10 @@ def ensemble_run(ctxs, states, steps, cfl, block=0, stream=None):
 
 
 def ensemble_autotune(ctxs, states, reps=1, cfl=0.4, stream=None):
-    """Pick the ensemble workgroup size (256 / 512 / 1024) by timing `reps`
-    steps on copies of the states; returns it."""
+    """Pick the ensemble workgroup size (256 / 512 / 1024) and segment length
+    (whole pencils or about 96 / 64 / 48 / 32 interior zones) by timing `reps`
+    steps on copies of the states; sets the members' segments and returns the
+    workgroup size."""
     n, hs, sts, sp = _ensemble_args(ctxs, states, stream)
     b = C.c_int()
     rc = lib().ppmlr_ensemble_autotune(hs, sp, n, int(reps), float(cfl), C.byref(b))

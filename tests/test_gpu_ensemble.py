@@ -73,6 +73,34 @@ def test_ensemble_members_equal_solo_runs_bitwise(dtype, block):
         assert c.stats() == solo.stats()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_ensemble_with_segmented_members_equals_solo_runs_bitwise(dtype):
+    # members 0 and 2 cut their pencils into segments (on all axes, or on z
+    # only), members 1 and 3 keep whole pencils; 3 steps = 9 sweeps, so the
+    # alternating members end in their second state and are copied back
+    from paper_1607_02214_amd import ppmlr
+    mem = _members()
+    segs = [(3, 3, 3), (1, 1, 1), (1, 1, 2), (1, 1, 1)]
+    block = 256
+    ctxs = [_ctx(m) for m in mem]
+    for c, sg in zip(ctxs, segs):
+        for ax, k in enumerate(sg):
+            c.set_segments(ax, k)
+    us = [torch.from_numpy(m.U).to("cuda", dtype).contiguous() for m in mem]
+    status = ppmlr.ensemble_run(ctxs, us, 3, 0.4, block=block)
+    assert status == [0] * len(mem)
+    for m, (st, c, u) in enumerate(zip(mem, ctxs, us)):
+        solo = _ctx(st)                  # whole pencils, any tile: the same result
+        w = torch.from_numpy(st.U).to("cuda", dtype).contiguous()
+        solo.advance(w, 3, 0.4)
+        torch.cuda.synchronize()
+        if not torch.equal(u, w):
+            d = (u - w).abs().flatten(1).max(dim=1).values.tolist()
+            raise AssertionError(f"member {m} (segments {segs[m]}) differs: max |diff| per variable {d}")
+        assert c.time(u) == solo.time(w)
+        assert c.stats() == solo.stats()
+
+
 def test_ensemble_autotune_leaves_states_untouched_and_c4_members_run():
     from paper_1607_02214_amd import ppmlr
     spec = I.ensemble_members(count=32, seed=4)
@@ -84,6 +112,7 @@ def test_ensemble_autotune_leaves_states_untouched_and_c4_members_run():
     before = [u.clone() for u in us]
     block = ppmlr.ensemble_autotune(ctxs, us, reps=1)
     assert block in (256, 512, 1024)
+    GC.log(f"[ensemble] autotuned segments of member 0: {[ctxs[0].get_segments(a) for a in range(3)]}")
     for u, b in zip(us, before):
         assert torch.equal(u, b)
     assert all(c.get_step_index() == 0 for c in ctxs)
