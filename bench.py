@@ -283,7 +283,8 @@ def main():
                 ctx.set_tile(a, 1)
                 ctx.set_segments(a, shape[1][a])
                 ctx.set_tile(a, shape[0][a])
-        print(f"[bench] tiles {[ctx.get_tile(a) for a in range(3)]} segments {[ctx.get_segments(a) for a in range(3)]}"
+        pdt = ppmlr.F64 if dtype == torch.float64 else ppmlr.F32
+        print(f"[bench] tiles {[ctx.get_tile(a, pdt) for a in range(3)]} segments {[ctx.get_segments(a, pdt) for a in range(3)]}"
               f"{'' if shape is None else ' (given)'}", file=sys.stderr, flush=True)
         ctx.advance(u, warmup, args.cfl)
         torch.cuda.synchronize()

@@ -102,10 +102,11 @@ void ppmlr_default_options(ppmlr_options *opt);
  * coords: host face coordinates, copied to the device.  opt: NULL for the
  * defaults.  Returns EINVAL for a bad grid (counts, non-increasing faces,
  * mismatched periodic sides, non-periodic axis shorter than 7 zones, more
- * than 1010 zones along an axis: a pencil and its 14 ghosts must fit one
- * 1024-lane workgroup).  Every call that takes a state also returns EINVAL
+ * than 2^24 zones along an axis).  Pencils longer than one workgroup holds
+ * (1010 zones in FP32, 818 in FP64) are swept in segments (see
+ * ppmlr_set_segments).  Every call that takes a state also returns EINVAL
  * if one variable of it (nx ny nz elements) exceeds 4 GiB: FP32 grids up to
- * 1010^3 zones, FP64 up to 2^29 zones. */
+ * 2^30 zones, FP64 up to 2^29 zones. */
 ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coords *coords,
                           const ppmlr_options *opt, ppmlr_ctx **out);
 void ppmlr_destroy(ppmlr_ctx *ctx);
@@ -172,7 +173,9 @@ ppmlr_status ppmlr_kernel_times(ppmlr_ctx *ctx, double ms[3], long long launches
 ppmlr_status ppmlr_set_tile(ppmlr_ctx *ctx, int axis, int pencils);
 ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *pencils);
 
-/* Segments per pencil for sweeps along axis; 0 = automatic (one).  A sweep
+/* Segments per pencil for sweeps along axis; 0 = automatic: the fewest whose
+ * tile fits one workgroup for the state's dtype (one, unless the pencil is
+ * longer than 1010 zones in FP32 or 818 in FP64).  A sweep
  * tile then holds `pencils` pencil segments of ceil(N / segments) interior
  * zones (the last segment takes the rest) plus the 7 ghost zones on either
  * side that the reconstruction, Riemann solve and remap of the sweep
@@ -189,7 +192,7 @@ ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *penc
  * segment would be empty or shorter than 7 zones, or the current tile no
  * longer fits one workgroup. */
 ppmlr_status ppmlr_set_segments(ppmlr_ctx *ctx, int axis, int segments);
-ppmlr_status ppmlr_get_segments(const ppmlr_ctx *ctx, int axis, int *segments);
+ppmlr_status ppmlr_get_segments(const ppmlr_ctx *ctx, int axis, int dtype, int *segments);
 
 /* Tile autotuner: for each axis, times `reps` sweeps of every tile shape
  * (pencils per workgroup, and segments per pencil from 1 to 8) that fits one
@@ -212,7 +215,7 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, 
  * contexts the same step-counter parity; the contexts' dt, time, signal-speed
  * and counter buffers are used as by ppmlr_advance, so none of the contexts
  * may be in use elsewhere meanwhile.
- * block: workgroup size 256, 512 or 1024 (every pencil + 14 ghosts must fit;
+ * block: workgroup size 256, 512 or 1024 (every pencil segment + 14 ghosts must fit;
  * 1024 is FP32 only), or 0 for the value chosen by ppmlr_ensemble_autotune
  * (512 if it never ran); each member's pencils are cut into the segments
  * its context is set to (ppmlr_set_segments), and pencils per workgroup per

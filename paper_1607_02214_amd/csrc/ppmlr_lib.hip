@@ -169,10 +169,26 @@ int seg_len(int N, int nseg)
 
 constexpr int kMaxSegments = 8;           // autotuner's search range
 
-int seg_count(const ppmlr_ctx *c, int axis) { return c->seg[axis] > 0 ? c->seg[axis] : 1; }
+int stride_for(int threads, int elem);
+
+// Segments per pencil: the context's setting, or (0 = automatic) the fewest
+// whose tile of one pencil segment fits a workgroup and the LDS (one for
+// any FP32 pencil up to 1010 zones).
+int seg_count(const ppmlr_ctx *c, int axis, int elem)
+{
+    if (c->seg[axis] > 0) return c->seg[axis];
+    const int N = c->n[axis];
+    for (int k = 1; k <= N; ++k) {
+        const int L = seg_len(N, k);
+        if (L == 0) continue;
+        const int thr = block_threads(1, L + 2 * kG);
+        if (thr <= 1024 && stride_for(thr, elem) >= 0) return k;
+    }
+    return 1;
+}
 
 // Zones of one tile's pencil segment (interior + ghosts).
-int tile_M(const ppmlr_ctx *c, int axis) { return seg_len(c->n[axis], seg_count(c, axis)) + 2 * kG; }
+int tile_M(const ppmlr_ctx *c, int axis, int elem) { return seg_len(c->n[axis], seg_count(c, axis, elem)) + 2 * kG; }
 
 // Automatic tile: the number of pencils per workgroup that wastes the fewest
 // lanes (padding to whole waves plus ghost zones), within the thread budget.
@@ -192,7 +208,7 @@ int stride_for(int threads, int elem)
 
 int auto_tile(const ppmlr_ctx *c, int axis, int elem)
 {
-    const int N = seg_len(c->n[axis], seg_count(c, axis)), M = N + 2 * kG;
+    const int N = seg_len(c->n[axis], seg_count(c, axis, elem)), M = N + 2 * kG;
     const int cap = (elem == 8) ? 512 : 1024;
     const int nq = (axis == 0) ? c->n[1] : c->n[0];
     int best = 1;
@@ -372,11 +388,11 @@ ppmlr_status sweep_typed(ppmlr_ctx *c, const T *in, T *u, hipStream_t st, double
                          bool fuse)
 {
     const int P = pick_tile(c, axis, (int)sizeof(T));
-    const int M = tile_M(c, axis);
+    const int M = tile_M(c, axis, (int)sizeof(T));
     if (block_threads(P, M) > 1024 || (size_t)(kSlotsA + kSlotsB) * P * M * sizeof(T) > 160 * 1024)
         return fail(c, PPMLR_EINVAL, "tile does not fit one workgroup");
     ppmlr::SweepArgs<T> a;
-    fill_args(c, a, in, u, axis, dt, dt_dev, P, seg_count(c, axis));
+    fill_args(c, a, in, u, axis, dt, dt_dev, P, seg_count(c, axis, (int)sizeof(T)));
     const bool stats = c->opt.collect_stats != 0;
     if (axis == 0) return launch_axis<0, T>(c, a, st, stats, fuse);
     if (axis == 1) return launch_axis<1, T>(c, a, st, stats, fuse);
@@ -452,7 +468,7 @@ ppmlr_status do_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, const doubl
 {
     hipStream_t st = (hipStream_t)s->stream;
     void *out = f.home;
-    if (seg_count(c, axis) > 1) {
+    if (seg_count(c, axis, s->dtype == PPMLR_F64 ? 8 : 4) > 1) {
         ppmlr_status e = ensure_pong(c, state_bytes(c, s));
         if (e) return e;
         out = (f.cur == f.home) ? c->d_pong : f.home;
@@ -682,7 +698,7 @@ ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coor
         if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return PPMLR_EINVAL;
         if ((lo == PPMLR_PERIODIC) != (hi == PPMLR_PERIODIC)) return PPMLR_EINVAL;
         if (lo != PPMLR_PERIODIC && grid->n[a] < kG) return PPMLR_EINVAL;
-        if (grid->n[a] + 2 * kG > 1024) return PPMLR_EINVAL;   // one pencil per workgroup at most
+        if (grid->n[a] > (1 << 24)) return PPMLR_EINVAL;     // 32-bit zone indexing with margin
         for (int i = 0; i < grid->n[a]; ++i)
             if (!(coords->faces[a][i + 1] > coords->faces[a][i]) || !std::isfinite(coords->faces[a][i + 1]))
                 return PPMLR_EINVAL;
@@ -999,7 +1015,7 @@ ppmlr_status ppmlr_set_tile(ppmlr_ctx *c, int axis, int pencils)
 {
     if (!c || axis < 0 || axis > 2 || pencils < 0) return PPMLR_EINVAL;
     if (pencils > 0) {
-        int M = tile_M(c, axis);
+        int M = tile_M(c, axis, 4);
         if (block_threads(pencils, M) > 1024) return fail(c, PPMLR_EINVAL, "tile exceeds 1024 threads");
         if ((size_t)(kSlotsA + kSlotsB) * pencils * M * 4 > 160 * 1024)
             return fail(c, PPMLR_EINVAL, "tile exceeds the LDS budget");
@@ -1011,19 +1027,25 @@ ppmlr_status ppmlr_set_tile(ppmlr_ctx *c, int axis, int pencils)
 ppmlr_status ppmlr_set_segments(ppmlr_ctx *c, int axis, int segments)
 {
     if (!c || axis < 0 || axis > 2 || segments < 0) return PPMLR_EINVAL;
-    const int L = seg_len(c->n[axis], segments > 0 ? segments : 1);
-    if (L == 0) return fail(c, PPMLR_EINVAL, "segment count leaves a segment empty");
-    if (segments > 1 && L < kG) return fail(c, PPMLR_EINVAL, "segments shorter than the ghost width");
-    if (c->tile[axis] > 0 && block_threads(c->tile[axis], L + 2 * kG) > 1024)
-        return fail(c, PPMLR_EINVAL, "tile exceeds 1024 threads");
+    const int old = c->seg[axis];
     c->seg[axis] = segments;
+    const int k = seg_count(c, axis, 4);
+    const int L = seg_len(c->n[axis], k);
+    const char *why = nullptr;
+    if (L == 0) why = "segment count leaves a segment empty";
+    else if (k > 1 && L < kG) why = "segments shorter than the ghost width";
+    else if (c->tile[axis] > 0 && block_threads(c->tile[axis], L + 2 * kG) > 1024) why = "tile exceeds 1024 threads";
+    if (why) {
+        c->seg[axis] = old;
+        return fail(c, PPMLR_EINVAL, why);
+    }
     return PPMLR_OK;
 }
 
-ppmlr_status ppmlr_get_segments(const ppmlr_ctx *c, int axis, int *segments)
+ppmlr_status ppmlr_get_segments(const ppmlr_ctx *c, int axis, int dtype, int *segments)
 {
     if (!c || axis < 0 || axis > 2 || !segments) return PPMLR_EINVAL;
-    *segments = seg_count(c, axis);
+    *segments = seg_count(c, axis, dtype == PPMLR_F64 ? 8 : 4);
     return PPMLR_OK;
 }
 
@@ -1121,7 +1143,7 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
     std::vector<char> pp(n, 0);
     for (int m = 0; m < n; ++m) {
         for (int ax = 0; ax < 3; ++ax)
-            if (seg_count(ctxs[m], ax) > 1) pp[m] = 1;
+            if (seg_count(ctxs[m], ax, (int)sizeof(T)) > 1) pp[m] = 1;
         if (pp[m]) {
             ppmlr_status e = ensure_pong(ctxs[m], state_bytes(ctxs[m], states[m]));
             if (e) return e;
@@ -1138,8 +1160,8 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         for (int m = 0; m < n; ++m) {
             ppmlr_ctx *c = ctxs[m];
             if (c->opt.collect_stats) stats = true;
-            const int nseg = seg_count(c, ax);
-            const int M = tile_M(c, ax);
+            const int nseg = seg_count(c, ax, (int)sizeof(T));
+            const int M = tile_M(c, ax, (int)sizeof(T));
             const int nq = (ax == 0) ? c->n[1] : c->n[0];
             const int P = std::max(1, std::min(block / M, nq));
             T *home = (T *)states[m]->u, *pong = (T *)c->d_pong;
@@ -1249,8 +1271,10 @@ ppmlr_status ensemble_check(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         if (states[m]->dtype != states[0]->dtype) return fail(ctxs[0], PPMLR_EINVAL, "members differ in dtype");
         if (states[m]->stream != states[0]->stream) return fail(ctxs[0], PPMLR_EINVAL, "members differ in stream");
         if ((ctxs[m]->step & 1) != (ctxs[0]->step & 1)) return fail(ctxs[0], PPMLR_EINVAL, "step parity differs");
+        const int elem = states[m]->dtype == PPMLR_F64 ? 8 : 4;
         for (int a = 0; a < 3; ++a)
-            if (ctxs[m]->n[a] + 2 * kG > block) return fail(ctxs[0], PPMLR_EINVAL, "a pencil does not fit the block");
+            if (tile_M(ctxs[m], a, elem) > block)
+                return fail(ctxs[0], PPMLR_EINVAL, "a pencil segment does not fit the block");
     }
     if (block != 256 && block != 512 && block != 1024) return fail(ctxs[0], PPMLR_EINVAL, "block must be 256, 512 or 1024");
     if (block == 1024 && states[0]->dtype == PPMLR_F64) return fail(ctxs[0], PPMLR_EINVAL, "FP64 block <= 512");
@@ -1316,7 +1340,7 @@ ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *
         for (int m = 0; m < n; ++m)
             for (int ax = 0; ax < 3; ++ax) {
                 const int N = ctxs[m]->n[ax];
-                int k = len > 0 ? (N + len - 1) / len : 1;
+                int k = len > 0 ? (N + len - 1) / len : 0;   // 0: whole pencils where they fit
                 while (k > 1 && (seg_len(N, k) == 0 || seg_len(N, k) < kG)) --k;
                 ctxs[m]->seg[ax] = k;
             }
@@ -1326,8 +1350,8 @@ ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *
     if (!e) e = hip_check(ctxs[0], hipEventCreate(&t1), "hipEventCreate");
     for (int cand = 0; cand < 15 && !e; ++cand) {
         const int B = cands[cand / 5], len = lens[cand % 5];
-        if (ensemble_check(ctxs, tptr.data(), n, reps, cfl, B) != PPMLR_OK) continue;
         set_lengths(len);
+        if (ensemble_check(ctxs, tptr.data(), n, reps, cfl, B) != PPMLR_OK) continue;
         e = hip_check(ctxs[0], hipEventRecord(t0, st), "hipEventRecord");
         if (!e) e = ppmlr_ensemble_run(ctxs, tptr.data(), n, reps, cfl, B, nullptr);
         if (!e) e = hip_check(ctxs[0], hipEventRecord(t1, st), "hipEventRecord");

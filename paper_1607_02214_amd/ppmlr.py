@@ -117,7 +117,7 @@ SIGNATURES = {
     "ppmlr_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "ppmlr_get_tile": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_set_segments": (C.c_int, [_P, C.c_int, C.c_int]),
-    "ppmlr_get_segments": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
+    "ppmlr_get_segments": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_autotune": (C.c_int, [_P, C.POINTER(State), C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_ensemble_run": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
                                      C.c_int, C.POINTER(C.c_int)]),
@@ -299,9 +299,9 @@ class Context:
     def set_segments(self, axis, segments):
         return self._chk(lib().ppmlr_set_segments(self.h, int(axis), int(segments)))
 
-    def get_segments(self, axis):
+    def get_segments(self, axis, dtype=F32):
         v = C.c_int()
-        self._chk(lib().ppmlr_get_segments(self.h, int(axis), C.byref(v)))
+        self._chk(lib().ppmlr_get_segments(self.h, int(axis), int(dtype), C.byref(v)))
         return v.value
 
     def autotune(self, u, reps=3, stream=None):

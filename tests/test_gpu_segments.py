@@ -159,3 +159,37 @@ def test_full_size_z_sweep_segments_bitwise():
             ref = u
         else:
             assert torch.equal(u, ref), k
+
+
+@pytest.mark.parametrize("shape,axis", [((1100, 8, 7), 0), ((7, 8, 900), 2)])
+def test_long_pencils_use_segments_and_match_oracle(shape, axis):
+    # pencils longer than one workgroup holds (1010 zones FP32, 818 FP64)
+    # are swept in segments automatically; one FP64 step against the oracle
+    from oracle import oracle as O
+    from paper_1607_02214_amd import ppmlr
+    case = GC.blast_case(n=shape, seed=7)
+    ctx = case.context()
+    n = shape[axis]
+    assert ctx.get_segments(axis, ppmlr.F64) == 2
+    assert ctx.get_segments(axis, ppmlr.F32) == (2 if n > 1010 else 1)
+    ora = case.oracle()
+    dt = ora.cfl_dt(case.U, 0.4)
+    st = O.Stats()
+    ref = ora.step(case.U, dt, 0, st)
+    GC.log(f"[segments] long pencils {shape} axis {axis}: FP64 step vs oracle")
+    u = torch.from_numpy(case.U).cuda().contiguous()
+    ctx.step(u, dt)
+    torch.cuda.synchronize()
+    err = GC.normwise_errors(u.cpu().numpy(), ref)
+    assert np.all(err <= 1e-11), err
+    assert ctx.stats()["nonconverged"] == st.nonconverged == 0
+    # FP32: automatic segments equal three explicit segments bitwise
+    res = []
+    for k in (0, 3):
+        c = case.context()
+        c.set_segments(axis, k)
+        w = torch.from_numpy(case.U).to("cuda", torch.float32).contiguous()
+        c.step(w, dt)
+        torch.cuda.synchronize()
+        res.append(w)
+    assert torch.equal(res[0], res[1])
