@@ -246,6 +246,7 @@ def main():
     ap.add_argument("--tiles", type=str, default=None,
                     help="pencils per tile x,y,z for the FP32 run (with --segments: no autotuning)")
     ap.add_argument("--segments", type=str, default=None, help="segments per pencil x,y,z for the FP32 run")
+    ap.add_argument("--order", type=str, default=None, help="segment tile order x,y,z (1 adjacent, 2 bands) with --tiles")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -283,8 +284,11 @@ def main():
                 ctx.set_tile(a, 1)
                 ctx.set_segments(a, shape[1][a])
                 ctx.set_tile(a, shape[0][a])
+                if shape[2] is not None:
+                    ctx.set_segment_order(a, shape[2][a])
         pdt = ppmlr.F64 if dtype == torch.float64 else ppmlr.F32
         print(f"[bench] tiles {[ctx.get_tile(a, pdt) for a in range(3)]} segments {[ctx.get_segments(a, pdt) for a in range(3)]}"
+              f" order {[ctx.get_segment_order(a) for a in range(3)]}"
               f"{'' if shape is None else ' (given)'}", file=sys.stderr, flush=True)
         ctx.advance(u, warmup, args.cfl)
         torch.cuda.synchronize()
@@ -319,7 +323,8 @@ def main():
     if args.tiles or args.segments:
         if not (args.tiles and args.segments):
             raise SystemExit("--tiles and --segments go together")
-        shape = ([int(x) for x in args.tiles.split(",")], [int(x) for x in args.segments.split(",")])
+        shape = ([int(x) for x in args.tiles.split(",")], [int(x) for x in args.segments.split(",")],
+                 [int(x) for x in args.order.split(",")] if args.order else None)
     ctx, u, ms, wall, kms, kn, status, st, finite = run(torch.float32, args.steps, args.warmup, shape=shape)
     value = zones * args.steps / (ms / 1000.0)
     avg = [kms[a] / kn[a] if kn[a] else 0.0 for a in range(3)]
@@ -363,6 +368,7 @@ def main():
             "cfl": args.cfl,
             "tiles": [ctx.get_tile(a, ppmlr.F32) for a in range(3)],
             "segments": [ctx.get_segments(a) for a in range(3)],
+            "segment_order": [ctx.get_segment_order(a) for a in range(3)],
             "tile_search": "autotuned" if shape is None else "given",
         },
         "roofline": roofline,

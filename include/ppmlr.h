@@ -192,10 +192,18 @@ ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *penc
  * segment would be empty or shorter than 7 zones, or the current tile no
  * longer fits one workgroup. */
 ppmlr_status ppmlr_set_segments(ppmlr_ctx *ctx, int axis, int segments);
+/* Tile order of segmented sweeps along axis: 1 = the segments of one pencil
+ * group are consecutive tiles, 2 = the grid is dealt out one segment band
+ * after another (the tiles running together then touch fewer state planes),
+ * 0 = automatic (1 for x, 2 for y and z).  Results do not depend on it.
+ * ppmlr_get_segment_order returns the order in effect (1 or 2). */
+ppmlr_status ppmlr_set_segment_order(ppmlr_ctx *ctx, int axis, int order);
+ppmlr_status ppmlr_get_segment_order(const ppmlr_ctx *ctx, int axis, int *order);
 ppmlr_status ppmlr_get_segments(const ppmlr_ctx *ctx, int axis, int dtype, int *segments);
 
 /* Tile autotuner: for each axis, times `reps` sweeps of every tile shape
- * (pencils per workgroup, and segments per pencil from 1 to 8) that fits one
+ * (pencils per workgroup, segments per pencil from 1 to 8, both segment
+ * orders) that fits one
  * workgroup on a library-owned copy of the state (the caller's state is not
  * modified), keeps the fastest per axis (both are set on the context) and
  * returns the pencils per workgroup in tiles[3] (may be NULL).  The sweeps timed use the context's initial-guess mode

@@ -48,7 +48,8 @@ struct ppmlr_ctx {
     int partial_blocks = 0;
     long long step = 0;
     int tile[3] = {0, 0, 0};
-    int seg[3] = {0, 0, 0};                  // segments per pencil (0: one)
+    int seg[3] = {0, 0, 0};                  // segments per pencil (0: automatic)
+    int seg_order[3] = {0, 0, 0};            // tile order of segments (0: automatic, 1: adjacent, 2: bands)
     void *d_pong = nullptr;                  // second state for segmented sweeps
     size_t pong_bytes = 0;
     int device = 0;
@@ -187,6 +188,17 @@ int seg_count(const ppmlr_ctx *c, int axis, int elem)
     return 1;
 }
 
+// Whether the segments of a pencil group are adjacent in the tile order (1)
+// or the grid is dealt out one segment band after another (0).  Automatic:
+// adjacent for x, bands for y and z (measured on the 256x192x192 sweeps:
+// bands take the z sweep from 0.42 to 0.36 ms, cost x 10 %).
+int seg_fast_for(const ppmlr_ctx *c, int axis)
+{
+    if (c->seg_order[axis] == 1) return 1;
+    if (c->seg_order[axis] == 2) return 0;
+    return axis == 0 ? 1 : 0;
+}
+
 // Zones of one tile's pencil segment (interior + ghosts).
 int tile_M(const ppmlr_ctx *c, int axis, int elem) { return seg_len(c->n[axis], seg_count(c, axis, elem)) + 2 * kG; }
 
@@ -258,7 +270,7 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, const T *in, T *u, in
     a.L = L;
     a.nseg = nseg;
     a.Mext = N + 2 * kG;
-    a.seg_fast = 1;
+    a.seg_fast = seg_fast_for(c, axis);
     a.P = P;
     a.S = P * M;
     int qax, rax;
@@ -1042,6 +1054,20 @@ ppmlr_status ppmlr_set_segments(ppmlr_ctx *c, int axis, int segments)
     return PPMLR_OK;
 }
 
+ppmlr_status ppmlr_set_segment_order(ppmlr_ctx *c, int axis, int order)
+{
+    if (!c || axis < 0 || axis > 2 || order < 0 || order > 2) return PPMLR_EINVAL;
+    c->seg_order[axis] = order;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_get_segment_order(const ppmlr_ctx *c, int axis, int *order)
+{
+    if (!c || axis < 0 || axis > 2 || !order) return PPMLR_EINVAL;
+    *order = seg_fast_for(c, axis) ? 1 : 2;
+    return PPMLR_OK;
+}
+
 ppmlr_status ppmlr_get_segments(const ppmlr_ctx *c, int axis, int dtype, int *segments)
 {
     if (!c || axis < 0 || axis > 2 || !segments) return PPMLR_EINVAL;
@@ -1073,14 +1099,17 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
     ppmlr_state tmp = *s;
     tmp.u = scratch;
     for (int axis = 0; axis < 3 && !e; ++axis) {
-        int best = 1, best_seg = 1;
+        int best = 1, best_seg = 1, best_order = 0;
         float best_ms = 1e30f;
-        for (int nseg = 1; nseg <= kMaxSegments && !e; ++nseg) {
+        for (int cand = 0; cand < 2 * kMaxSegments && !e; ++cand) {
+            const int nseg = 1 + cand / 2, order = 1 + cand % 2;
+            if (nseg == 1 && order == 2) continue;         // one segment: no order
             const int L = seg_len(c->n[axis], nseg);
             if (L == 0) continue;
             if (L < kG) break;
             const int M = L + 2 * kG;
             c->seg[axis] = nseg;
+            c->seg_order[axis] = nseg == 1 ? 0 : order;
             for (int P = 1; P <= 32 && !e; ++P) {
                 const int thr = block_threads(P, M);
                 if (thr > 1024) break;
@@ -1095,11 +1124,12 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
                 if (!e) e = hip_check(c, hipEventSynchronize(t1), "hipEventSynchronize");
                 float ms = 0.0f;
                 if (!e) e = hip_check(c, hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
-                if (!e && ms < best_ms) { best_ms = ms; best = P; best_seg = nseg; }
+                if (!e && ms < best_ms) { best_ms = ms; best = P; best_seg = nseg; best_order = c->seg_order[axis]; }
             }
         }
         c->tile[axis] = best;
         c->seg[axis] = best_seg;
+        c->seg_order[axis] = best_order;
         if (tiles) tiles[axis] = best;
     }
     c->profiling = prof;

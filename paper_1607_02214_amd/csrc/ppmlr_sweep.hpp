@@ -1081,8 +1081,9 @@ __global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepA
     }
     const SweepArgs<T> &a = e.desc[lo];
     const int t = j - e.mo[lo];
-    const int seg = t % a.nseg;                   // segments of a pencil group adjacent
-    const int tt = t / a.nseg;
+    int seg, tt;                                  // as in the single-run order
+    if (a.seg_fast) { seg = t % a.nseg; tt = t / a.nseg; }
+    else { seg = t / a.ntiles; tt = t - seg * a.ntiles; }
     const int tq = tt % a.tiles_q;
     const int r = tt / a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;

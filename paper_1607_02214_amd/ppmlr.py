@@ -117,6 +117,8 @@ SIGNATURES = {
     "ppmlr_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "ppmlr_get_tile": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_set_segments": (C.c_int, [_P, C.c_int, C.c_int]),
+    "ppmlr_set_segment_order": (C.c_int, [_P, C.c_int, C.c_int]),
+    "ppmlr_get_segment_order": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_get_segments": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_autotune": (C.c_int, [_P, C.POINTER(State), C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_ensemble_run": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
@@ -298,6 +300,14 @@ class Context:
 
     def set_segments(self, axis, segments):
         return self._chk(lib().ppmlr_set_segments(self.h, int(axis), int(segments)))
+
+    def set_segment_order(self, axis, order):
+        return self._chk(lib().ppmlr_set_segment_order(self.h, int(axis), int(order)))
+
+    def get_segment_order(self, axis):
+        v = C.c_int()
+        self._chk(lib().ppmlr_get_segment_order(self.h, int(axis), C.byref(v)))
+        return v.value
 
     def get_segments(self, axis, dtype=F32):
         v = C.c_int()

@@ -35,9 +35,10 @@ def _segments_for(n):
     return out
 
 
-def _sweep(case, dtype, axis, segments, dt):
+def _sweep(case, dtype, axis, segments, dt, order=0):
     ctx = case.context()
     ctx.set_segments(axis, segments)
+    ctx.set_segment_order(axis, order)
     u = torch.from_numpy(case.U).to("cuda", dtype).contiguous()
     ctx.reset_stats()
     ctx.sweep(u, dt, axis)
@@ -56,10 +57,11 @@ def test_segmented_sweep_is_bitwise_whole_pencil(maker, dtype):
     for axis in range(3):
         ref, st_ref = _sweep(case, dtype, axis, 1, dt)
         for k in _segments_for(n[axis]):
-            GC.log(f"[segments] {case.name} {dtype} axis {axis} N={n[axis]} segments {k}")
-            got, st = _sweep(case, dtype, axis, k, dt)
-            assert torch.equal(got, ref), (axis, k)
-            assert st == st_ref, (axis, k)
+            for order in (1, 2):             # segments adjacent / segment bands
+                GC.log(f"[segments] {case.name} {dtype} axis {axis} N={n[axis]} segments {k} order {order}")
+                got, st = _sweep(case, dtype, axis, k, dt, order)
+                assert torch.equal(got, ref), (axis, k, order)
+                assert st == st_ref, (axis, k, order)
 
 
 def test_segmented_advance_matches_whole_pencils():
@@ -116,6 +118,9 @@ def test_segment_arguments():
     case = GC.blast_case()                 # n = 40, 33, 30
     ctx = case.context()
     assert ctx.get_segments(0) == 1
+    assert [ctx.get_segment_order(a) for a in range(3)] == [1, 2, 2]
+    with pytest.raises(ppmlr.PPMLRError):
+        ctx.set_segment_order(0, 3)
     ctx.set_segments(0, 5)                 # segments of 8
     assert ctx.get_segments(0) == 5
     with pytest.raises(ppmlr.PPMLRError):
