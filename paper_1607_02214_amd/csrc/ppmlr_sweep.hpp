@@ -907,7 +907,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     __syncthreads();
 
     // ------------------------------------------------------------ R8
-    double smax = 0.0;
+    // signal-speed maximum in the sweep's precision: a maximum selects one
+    // value, so reducing in FP32 and converting the result gives the FP64
+    // maximum of the converted values exactly
+    T smax = T(0);
     if (interior) {
         T out[8];
         const T idx = Ar<T>::rcp(dxi);
@@ -959,12 +962,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             const T px = out[4], py = out[5], pz = out[6];
             T p_ = (gam - T(1)) * (out[7] - T(0.5) * r_ * (vx * vx + vy * vy + vz * vz) -
                                    T(0.5) * (px * px + py * py + pz * pz));
-            p_ = tmax(p_, a.p_floor);
+            // fmax / fabs where they agree with the selects for every input
+            // (a NaN p or discriminant gives the floor / zero either way);
+            // the running maximum keeps its select, which passes a NaN on
+            p_ = fmax_(p_, a.p_floor);
             T Bx = px, By = py, Bz = pz;
             if (a.has_bd) {
-                T bx, by, bz, x, y, z;
-                to_xyz<AX>(xci, c1, c2, x, y, z);
-                background(a, x, y, z, bx, by, bz);
+                // the zone-centre background field of R1, back from the pencil frame
+                T bx, by, bz;
+                to_xyz<AX>(bdn, bd1, bd2, bx, by, bz);
                 Bx += bx; By += by; Bz += bz;
             }
             const T a2 = gam * p_ * ir;
@@ -974,21 +980,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             const T wx = elem(a.dxw_x, ix), wy = elem(a.dxw_y, iy), wz = elem(a.dxw_z, iz);
             T sp = T(0);
             {
-                T disc = tmax(s2 * s2 - q4 * Bx * Bx, T(0));
+                T disc = fmax_(s2 * s2 - q4 * Bx * Bx, T(0));
                 T cf = Ar<T>::sqrt_(T(0.5) * (s2 + Ar<T>::sqrt_(disc)));
-                sp = tmax(sp, (tabs(vx) + cf) * Ar<T>::rcp(wx));
+                sp = tmax(sp, (fabs_(vx) + cf) * Ar<T>::rcp(wx));
             }
             {
-                T disc = tmax(s2 * s2 - q4 * By * By, T(0));
+                T disc = fmax_(s2 * s2 - q4 * By * By, T(0));
                 T cf = Ar<T>::sqrt_(T(0.5) * (s2 + Ar<T>::sqrt_(disc)));
-                sp = tmax(sp, (tabs(vy) + cf) * Ar<T>::rcp(wy));
+                sp = tmax(sp, (fabs_(vy) + cf) * Ar<T>::rcp(wy));
             }
             {
-                T disc = tmax(s2 * s2 - q4 * Bz * Bz, T(0));
+                T disc = fmax_(s2 * s2 - q4 * Bz * Bz, T(0));
                 T cf = Ar<T>::sqrt_(T(0.5) * (s2 + Ar<T>::sqrt_(disc)));
-                sp = tmax(sp, (tabs(vz) + cf) * Ar<T>::rcp(wz));
+                sp = tmax(sp, (fabs_(vz) + cf) * Ar<T>::rcp(wz));
             }
-            smax = (double)sp;
+            smax = sp;
         }
     }
     if (STATS) {
@@ -999,10 +1005,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     if (FUSE_CFL) {
         // wave max (all lanes active), workgroup max, one atomic per workgroup
         for (int off = 32; off > 0; off >>= 1) {
-            double o = __shfl_xor(smax, off);
+            T o = __shfl_xor(smax, off);
             smax = o > smax ? o : smax;
         }
-        if (__lane_id() == 0) s_red[tid >> 6] = smax;
+        if (__lane_id() == 0) s_red[tid >> 6] = (double)smax;
         __syncthreads();
         if (tid == 0) {
             double m = 0.0;
