@@ -205,8 +205,9 @@ ppmlr_status ppmlr_get_segments(const ppmlr_ctx *ctx, int axis, int dtype, int *
  * (pencils per workgroup, segments per pencil from 1 to 8, both segment
  * orders) that fits one
  * workgroup on a library-owned copy of the state (the caller's state is not
- * modified), keeps the fastest per axis (both are set on the context) and
- * returns the pencils per workgroup in tiles[3] (may be NULL).  The sweeps timed use the context's initial-guess mode
+ * modified), times the three fastest again with 3 x reps sweeps, keeps the
+ * fastest per axis (the shape is set on the context) and returns the pencils
+ * per workgroup in tiles[3] (may be NULL).  The sweeps timed use the context's initial-guess mode
  * (the harvest mode is timed as the plain one and records nothing); they add
  * to the counters.  Synchronises; allocates and frees one state-sized buffer. */
 ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, int tiles[3]);

@@ -1098,9 +1098,23 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
     if (guess == PPMLR_GUESS_HARVEST) c->guess = PPMLR_GUESS_PLAIN;
     ppmlr_state tmp = *s;
     tmp.u = scratch;
+    // time `r` sweeps of the current shape on a fresh copy of the state
+    auto time_shape = [&](int axis, int r, float &ms) -> ppmlr_status {
+        ppmlr_status e2 = hip_check(c, hipMemcpyAsync(scratch, s->u, bytes, hipMemcpyDeviceToDevice, st),
+                                    "hipMemcpyAsync");
+        Flow f{scratch, scratch};
+        if (!e2) e2 = do_sweep(c, &tmp, dt, nullptr, axis, false, f);   // warm-up
+        if (!e2) e2 = hip_check(c, hipEventRecord(t0, st), "hipEventRecord");
+        for (int k = 0; k < r && !e2; ++k) e2 = do_sweep(c, &tmp, dt, nullptr, axis, false, f);
+        if (!e2) e2 = hip_check(c, hipEventRecord(t1, st), "hipEventRecord");
+        if (!e2) e2 = hip_check(c, hipEventSynchronize(t1), "hipEventSynchronize");
+        if (!e2) e2 = hip_check(c, hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+        ms /= (float)r;
+        return e2;
+    };
+    struct Shape { float ms; int P, nseg, order; };
     for (int axis = 0; axis < 3 && !e; ++axis) {
-        int best = 1, best_seg = 1, best_order = 0;
-        float best_ms = 1e30f;
+        std::vector<Shape> shapes;
         for (int cand = 0; cand < 2 * kMaxSegments && !e; ++cand) {
             const int nseg = 1 + cand / 2, order = 1 + cand % 2;
             if (nseg == 1 && order == 2) continue;         // one segment: no order
@@ -1115,22 +1129,27 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
                 if (thr > 1024) break;
                 if (stride_for(thr, (int)elem) < 0) continue;
                 c->tile[axis] = P;
-                e = hip_check(c, hipMemcpyAsync(scratch, s->u, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-                Flow f{scratch, scratch};
-                if (!e) e = do_sweep(c, &tmp, dt, nullptr, axis, false, f);   // warm-up
-                if (!e) e = hip_check(c, hipEventRecord(t0, st), "hipEventRecord");
-                for (int r = 0; r < reps && !e; ++r) e = do_sweep(c, &tmp, dt, nullptr, axis, false, f);
-                if (!e) e = hip_check(c, hipEventRecord(t1, st), "hipEventRecord");
-                if (!e) e = hip_check(c, hipEventSynchronize(t1), "hipEventSynchronize");
                 float ms = 0.0f;
-                if (!e) e = hip_check(c, hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
-                if (!e && ms < best_ms) { best_ms = ms; best = P; best_seg = nseg; best_order = c->seg_order[axis]; }
+                e = time_shape(axis, reps, ms);
+                if (!e) shapes.push_back({ms, P, nseg, c->seg_order[axis]});
             }
         }
-        c->tile[axis] = best;
-        c->seg[axis] = best_seg;
-        c->seg_order[axis] = best_order;
-        if (tiles) tiles[axis] = best;
+        // the three fastest again, with three times the repetitions
+        std::sort(shapes.begin(), shapes.end(), [](const Shape &x, const Shape &y) { return x.ms < y.ms; });
+        Shape best = shapes.empty() ? Shape{0.0f, 1, 1, 0} : shapes[0];
+        float best_ms = 1e30f;
+        for (size_t k = 0; k < shapes.size() && k < 3 && !e; ++k) {
+            c->seg[axis] = shapes[k].nseg;
+            c->seg_order[axis] = shapes[k].order;
+            c->tile[axis] = shapes[k].P;
+            float ms = 0.0f;
+            e = time_shape(axis, 3 * reps, ms);
+            if (!e && ms < best_ms) { best_ms = ms; best = shapes[k]; }
+        }
+        c->tile[axis] = best.P;
+        c->seg[axis] = best.nseg;
+        c->seg_order[axis] = best.order;
+        if (tiles) tiles[axis] = best.P;
     }
     c->profiling = prof;
     c->guess = guess;
