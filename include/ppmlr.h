@@ -128,8 +128,10 @@ ppmlr_status ppmlr_set_inflow(ppmlr_ctx *ctx, const double prim[8]);
 ppmlr_status ppmlr_set_inner(ppmlr_ctx *ctx, double rho, double p);
 
 /* One 1D sweep along axis (0 = x, 1 = y, 2 = z) over every pencil of the
- * grid, in place (Section III-A: the 3D equations split into independent 1D
- * problems).  dt > 0.  Queued on state->stream. */
+ * grid (Section III-A: the 3D equations split into independent 1D
+ * problems); the result replaces the state (a segmented axis sweeps into
+ * the context's second state and copies back).  dt > 0.  Queued on
+ * state->stream. */
 ppmlr_status ppmlr_sweep(ppmlr_ctx *ctx, const ppmlr_state *state, double dt, int axis);
 
 /* One split step: x, y, z sweeps on even steps and z, y, x on odd steps

@@ -318,9 +318,8 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, const T *in, T *u, in
     }
     // plain tile order along q then r (grouping q tiles that share cache
     // lines before stepping r was measured on the z sweep and raised its
-    // fetched bytes, so it is left off)
-    a.group_q = a.tiles_q;
-    a.nslots = ((a.tiles_q + a.group_q - 1) / a.group_q) * a.group_q * a.nr;
+    // fetched bytes)
+    a.nslots = a.tiles_q * a.nr;
     a.tiles_per_xcd = (a.nslots * nseg + 7) / 8;
     a.mlp_frag = c->d_mlp_frag;
     a.mlp_theta = c->d_mlp_theta;

@@ -4,11 +4,11 @@
 // Riemann solve, remap onto the Eulerian grid; Section III-A: one independent
 // 1D problem per pencil).
 //
-// Execution model: one thread per zone, a workgroup owns P whole pencils
-// (N interior zones + 7 ghosts per side each), so the update is done in place
-// and every stencil is served from LDS.  Successive stages exchange only what
-// a neighbour needs, through two LDS buffers (A, B) with one barrier per
-// exchange:
+// Execution model: one thread per zone, a workgroup owns one tile of P
+// pencil segments (L interior zones + 7 ghosts per side each; one segment =
+// the whole pencil), and every stencil is served from LDS.  Successive stages
+// exchange only what a neighbour needs, through two LDS buffers (A, B) with
+// one barrier per exchange:
 //   R1 load + primitives                                  -> A
 //   R2 limited slopes (mass coordinate), shock test   A -> B
 //      edge values                                   A, B -> A (slots 9..15)
@@ -95,8 +95,7 @@ struct SweepArgs {
     T *var[8];                  // ... and of the output state (the same when whole pencils are swept in place)
     int nq, nr;                 // pencils along q (memory-fastest transverse) and r
     int tiles_q, ntiles, tiles_per_xcd;   // ntiles: tiles of one segment band (tiles_q * nr)
-    int group_q;                // tiles along q taken together before stepping r (>= 1)
-    int nslots;                 // tile slots of one segment band: ceil(tiles_q / group_q) * group_q * nr
+    int nslots;                 // tiles of one segment band: tiles_q * nr
     int seg_fast;               // 1: consecutive tiles are the segments of one pencil group; 0: bands in turn
     const T *dx, *xc, *xf;      // sweep axis: extended widths [Mext], centres [Mext], faces [Mext+1]
     const T *xc_q, *xc_r;       // transverse centres (interior zones)
@@ -1029,25 +1028,17 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     __shared__ unsigned int s_guess[1];
     // XCD-aware tile order: consecutive workgroups go to different XCDs
     // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
-    // tiles and share L2 lines of neighbouring pencils.  Within an XCD, groups
-    // of group_q tiles adjacent along q (sharing cache lines) run together and
-    // successive groups step along r, so that the lines in flight spread over
-    // many L2 sets when the pencil stride is a large power-of-two multiple
-    // (z sweeps).  Segments of a pencil are either adjacent in this order
-    // (seg_fast) or in successive bands of the whole grid.
+    // tiles (q fastest, then r) and share L2 lines of neighbouring pencils.
+    // The segments of a pencil group are either consecutive in this order
+    // (seg_fast) or the grid is dealt out one segment band after another.
     const int b = blockIdx.x;
     const int slot = (b & 7) * a.tiles_per_xcd + (b >> 3);
     if (slot >= a.nslots * a.nseg) return;
     int seg, tile;
     if (a.seg_fast) { seg = slot % a.nseg; tile = slot / a.nseg; }
     else { seg = slot / a.nslots; tile = slot - seg * a.nslots; }
-    const int gq = a.group_q;
-    const int gsz = gq * a.nr;
-    const int xg = tile / gsz;
-    const int rem = tile - xg * gsz;
-    const int r = rem / gq;
-    const int tq = xg * gq + (rem - r * gq);
-    if (tq >= a.tiles_q) return;
+    const int r = tile / a.tiles_q;
+    const int tq = tile - r * a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
     sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, seg, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat,
                                                   s_guess);

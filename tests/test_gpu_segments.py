@@ -198,3 +198,28 @@ def test_long_pencils_use_segments_and_match_oracle(shape, axis):
         torch.cuda.synchronize()
         res.append(w)
     assert torch.equal(res[0], res[1])
+
+
+def test_autotune_leaves_state_untouched_and_tuned_shape_is_bitwise_default():
+    # the tile search (pencils, segments, order) times sweeps on its own copy;
+    # whatever shape it picks, the run equals the default shape bitwise
+    case = GC.dipole_case()
+    ctx = case.context()
+    u = torch.from_numpy(case.U).to("cuda", torch.float32).contiguous()
+    before = u.clone()
+    tiles = ctx.autotune(u, reps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(u, before)
+    shape = [(ctx.get_tile(a), ctx.get_segments(a), ctx.get_segment_order(a)) for a in range(3)]
+    GC.log(f"[segments] autotuned (pencils, segments, order) per axis: {shape}")
+    assert [s[0] for s in shape] == list(tiles)
+    assert all(o in (1, 2) for _, _, o in shape)
+    ctx.reset_stats()
+    ctx.advance(u, 3, 0.4)
+    ref = case.context()
+    w = before.clone()
+    ref.advance(w, 3, 0.4)
+    torch.cuda.synchronize()
+    assert torch.equal(u, w)
+    assert ctx.time(u) == ref.time(w)
+    assert ctx.stats() == ref.stats()
