@@ -134,3 +134,24 @@ def test_ensemble_rejects_bad_arguments():
         ppmlr.ensemble_run(ctxs, us, 1, 0.4, block=128)
     with pytest.raises(ppmlr.PPMLRError):
         ppmlr.ensemble_run(ctxs, [us[0], us[1].double()], 1, 0.4, block=256)
+
+
+def test_one_failing_member_leaves_the_others_running():
+    # member 0 starts with a negative density: its status reports it, and the
+    # other members advance exactly as solo runs
+    from paper_1607_02214_amd import ppmlr
+    mem = _members(3)
+    U0 = mem[0].U.copy()
+    U0[0, 5, 6, 7] = -1.0
+    ctxs = [_ctx(m) for m in mem]
+    states = [U0] + [m.U for m in mem[1:]]
+    us = [torch.from_numpy(U).to("cuda", torch.float32).contiguous() for U in states]
+    status = ppmlr.ensemble_run(ctxs, us, 2, 0.4, block=256)
+    assert status[0] == ppmlr.PPMLR_ENONPHYS
+    assert status[1:] == [0, 0]
+    for m in (1, 2):
+        solo = _ctx(mem[m])
+        w = torch.from_numpy(mem[m].U).to("cuda", torch.float32).contiguous()
+        solo.advance(w, 2, 0.4)
+        torch.cuda.synchronize()
+        assert torch.equal(us[m], w), m

@@ -229,6 +229,13 @@ def test_error_paths():
     ub = _dev(Ub)
     ctx.sweep(ub, 1e-4, 0)
     assert ctx.status_check() == ppmlr.PPMLR_ENONPHYS
+    # NaN in the input -> ENONPHYS through the status check
+    Un = case.U.copy()
+    Un[7, 2, 3, 4] = np.nan
+    ctx.reset_stats()
+    ctx.sweep(_dev(Un), 1e-4, 1)
+    assert ctx.status_check() == ppmlr.PPMLR_ENONPHYS
+    assert ctx.stats()["nonphys"] >= 1
     # Newton limit reached -> ERIEMANN
     blast = GC.blast_case()
     ctx2 = blast.context(max_iter=1, tol_f64=1e-15)
