@@ -41,7 +41,7 @@ struct ppmlr_ctx {
     double inflow[8] = {1, 0, 0, 0, 0, 0, 0, 1};
     double inner_rho = 1.0, inner_p = 1.0;
     unsigned long long *d_stats = nullptr;   // kStatSlots x kStatWords
-    unsigned long long *d_cflmax = nullptr;  // signal-speed max (double bits)
+    unsigned long long *d_cflmax = nullptr;  // signal-speed max (double bits), kCflSlots slots
     double *d_dt = nullptr;                  // device-resident dt
     double *d_time = nullptr;                // accumulated simulated time
     double *d_partials = nullptr;            // totals partial sums
@@ -584,19 +584,47 @@ __global__ void __launch_bounds__(256) cfl_kernel(const CflArgs<T> a)
     if (threadIdx.x == 0) {
         double m = red[0];
         for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;
-        atomicMax(a.out, (unsigned long long)__double_as_longlong(m));
+        atomicMax(a.out + (blockIdx.x % ppmlr::kCflSlots) * ppmlr::kCflStride,
+                  (unsigned long long)__double_as_longlong(m));
     }
+}
+
+// Maximum of the signal-speed slots (one wave; the bits of non-negative
+// doubles order as unsigned integers, as for the atomics that filled them).
+__device__ inline unsigned long long slot_max(const unsigned long long *slots)
+{
+    unsigned long long v = slots[threadIdx.x * ppmlr::kCflStride];
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Fold the slots into slot 0 (one wave of kCflSlots threads).
+__global__ void fold_slots(unsigned long long *slots)
+{
+    const unsigned long long v = slot_max(slots);
+    slots[threadIdx.x * ppmlr::kCflStride] = threadIdx.x == 0 ? v : 0ull;
+}
+
+__global__ void clear_slots(unsigned long long *slots)
+{
+    slots[threadIdx.x * ppmlr::kCflStride] = 0ull;
 }
 
 // dt for the next step from the fused signal-speed maximum; accumulates the
 // simulated time and clears the maximum for the next reduction.
+// (one wave of kCflSlots threads)
 __global__ void dt_kernel(unsigned long long *smax_bits, double *dt, double *t, double cfl)
 {
-    double smax = __longlong_as_double((long long)*smax_bits);
+    const unsigned long long bits = slot_max(smax_bits);
+    smax_bits[threadIdx.x * ppmlr::kCflStride] = 0ull;
+    if (threadIdx.x != 0) return;
+    double smax = __longlong_as_double((long long)bits);
     double d = smax > 0.0 ? cfl / smax : 0.0;
     *dt = d;
     *t += d;
-    *smax_bits = 0ull;
 }
 
 __global__ void clear_u64(unsigned long long *p, int n)
@@ -673,7 +701,7 @@ ppmlr_status cfl_typed(ppmlr_ctx *c, const T *u, hipStream_t st)
 ppmlr_status cfl_launch(ppmlr_ctx *c, const ppmlr_state *s)
 {
     hipStream_t st = (hipStream_t)s->stream;
-    hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, st, c->d_cflmax, 1);
+    hipLaunchKernelGGL(clear_slots, dim3(1), dim3(ppmlr::kCflSlots), 0, st, c->d_cflmax);
     if (s->dtype == PPMLR_F64) return cfl_typed<double>(c, (const double *)s->u, st);
     return cfl_typed<float>(c, (const float *)s->u, st);
 }
@@ -752,13 +780,15 @@ ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coor
     c->partial_blocks = kTotBlocks;
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_stats, sizeof(unsigned long long) * kStatWords * kStatSlots),
                           "hipMalloc");
-    if (!s) s = hip_check(c, hipMalloc((void **)&c->d_cflmax, sizeof(unsigned long long)), "hipMalloc");
+    if (!s)
+        s = hip_check(c, hipMalloc((void **)&c->d_cflmax, sizeof(unsigned long long) * ppmlr::kCflSlots * ppmlr::kCflStride),
+                      "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_dt, sizeof(double)), "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_time, sizeof(double)), "hipMalloc");
     if (!s) s = hip_check(c, hipMalloc((void **)&c->d_partials, sizeof(double) * (8 * kTotBlocks + 8)), "hipMalloc");
     if (!s) {
         hipLaunchKernelGGL(clear_u64, dim3(1), dim3(256), 0, (hipStream_t)0, c->d_stats, kStatWords * kStatSlots);
-        hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_cflmax, 1);
+        hipLaunchKernelGGL(clear_slots, dim3(1), dim3(ppmlr::kCflSlots), 0, (hipStream_t)0, c->d_cflmax);
         hipLaunchKernelGGL(clear_f64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_dt, 1);
         hipLaunchKernelGGL(clear_f64, dim3(1), dim3(64), 0, (hipStream_t)0, c->d_time, 1);
         s = hip_check(c, hipDeviceSynchronize(), "init");
@@ -918,6 +948,7 @@ ppmlr_status ppmlr_cfl_dt(ppmlr_ctx *c, const ppmlr_state *s, double cfl, double
     if (e) return e;
     unsigned long long bits = 0;
     hipStream_t st = (hipStream_t)s->stream;
+    hipLaunchKernelGGL(fold_slots, dim3(1), dim3(ppmlr::kCflSlots), 0, st, c->d_cflmax);
     e = hip_check(c, hipMemcpyAsync(&bits, c->d_cflmax, sizeof(bits), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
     if (e) return e;
@@ -940,7 +971,7 @@ ppmlr_status ppmlr_advance(ppmlr_ctx *c, const ppmlr_state *s, int nsteps, doubl
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     Flow f{s->u, s->u};
     for (int n = 0; n < nsteps; ++n) {
-        hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(1), 0, st, c->d_cflmax, c->d_dt, c->d_time, cfl);
+        hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(ppmlr::kCflSlots), 0, st, c->d_cflmax, c->d_dt, c->d_time, cfl);
         const int *ord = (c->step % 2 == 0) ? even : odd;
         for (int k = 0; k < 3; ++k) {
             e = do_sweep(c, s, 0.0, c->d_dt, ord[k], k == 2, f);
@@ -1166,16 +1197,19 @@ namespace {
 int g_ensemble_block = 0;   // set by ppmlr_ensemble_autotune
 
 // dt of every member from its signal-speed maximum, exactly as dt_kernel
+// (one wave of kCflSlots threads per member)
 __global__ void ens_dt_kernel(unsigned long long *const *smax_bits, double *const *dt, double *const *t, int members,
                               double cfl)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.x;
     if (m >= members) return;
-    double smax = __longlong_as_double((long long)*smax_bits[m]);
+    const unsigned long long bits = slot_max(smax_bits[m]);
+    smax_bits[m][threadIdx.x * ppmlr::kCflStride] = 0ull;
+    if (threadIdx.x != 0) return;
+    double smax = __longlong_as_double((long long)bits);
     double d = smax > 0.0 ? cfl / smax : 0.0;
     *dt[m] = d;
     *t[m] += d;
-    *smax_bits[m] = 0ull;
 }
 
 template <typename T>
@@ -1257,7 +1291,7 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     long long j = 0;                                       // sweeps enqueued by this call
     for (int s = 0; s < steps && !err; ++s) {
-        hipLaunchKernelGGL(ens_dt_kernel, dim3((n + 63) / 64), dim3(64), 0, st, (unsigned long long *const *)d_ptr,
+        hipLaunchKernelGGL(ens_dt_kernel, dim3(n), dim3(ppmlr::kCflSlots), 0, st, (unsigned long long *const *)d_ptr,
                            (double *const *)(d_ptr + n), (double *const *)(d_ptr + 2 * (size_t)n), n, cfl);
         const int *ord = ((c0->step + s) % 2 == 0) ? even : odd;
         for (int k = 0; k < 3 && !err; ++k) {

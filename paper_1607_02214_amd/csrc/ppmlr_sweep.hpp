@@ -31,7 +31,13 @@ namespace ppmlr {
 constexpr int kG = 7;           // ghost zones per side
 constexpr int kSlotsA = 16;     // values per zone in LDS buffer A
 constexpr int kSlotsAGuess = 19;  // buffer A of the learned / harvest sweeps (3 more face values)
-constexpr int kSlotsB = 8;      // values per zone in LDS buffer B
+constexpr int kSlotsB = 8;
+// The signal-speed maximum is accumulated in kCflSlots words kCflStride
+// words apart (workgroup b uses slot b mod kCflSlots), so that the
+// workgroups' atomics do not all queue on one address; readers take the
+// maximum of the slots.
+constexpr int kCflSlots = 64;
+constexpr int kCflStride = 32;      // values per zone in LDS buffer B
 constexpr int kStatWords = 37;  // iteration histogram [32], floors, nonconverged, nonphys,
                                 // learned-guess faces, learned-guess fallbacks
 constexpr int kStatSlots = 64;  // copies of the counters (workgroup b adds to copy b % 64)
@@ -133,7 +139,7 @@ struct SweepArgs {
     int flatten, janhunen, max_iter;
     T tol, p_floor;
     unsigned long long *stats;  // kStatSlots x kStatWords counters or nullptr
-    unsigned long long *cfl_max;// fused signal-speed max (double bits) or nullptr
+    unsigned long long *cfl_max;// fused signal-speed max (double bits, kCflSlots slots) or nullptr
     const T *dxw_x, *dxw_y, *dxw_z;       // interior widths of all axes (fused CFL)
     // learned Riemann guess (FP32 single-run sweeps)
     const unsigned short *mlp_frag;       // packed BF16 weight fragments
@@ -1061,7 +1067,8 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024) sweep_kernel(const SweepAr
     const int r = tile / a.tiles_q;
     const int tq = tile - r * a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, seg, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat,
+    unsigned long long *cm = a.cfl_max ? a.cfl_max + (b % kCflSlots) * kCflStride : nullptr;
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, seg, dt, cm, b % kStatSlots, smem_raw, s_red, s_stat,
                                                   s_guess);
 }
 
@@ -1105,7 +1112,8 @@ __global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepA
     const int tq = tt % a.tiles_q;
     const int r = tt / a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, seg, dt, a.cfl_max, b % kStatSlots, smem_raw, s_red, s_stat);
+    unsigned long long *cm = a.cfl_max ? a.cfl_max + (b % kCflSlots) * kCflStride : nullptr;
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM>(a, tq, r, seg, dt, cm, b % kStatSlots, smem_raw, s_red, s_stat);
 }
 
 }  // namespace ppmlr
