@@ -103,6 +103,39 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
     }
 
 
+def series_leg(args, setup, make_ctx, shape_ctx):
+    """The FP32 run driven by a seeded synthetic solar-wind time series at
+    the inflow face (9 knots over the run's simulated time), with the plain
+    run's tile shape; timed like the plain run."""
+    import numpy as np
+    import torch
+    from paper_1607_02214_amd import inputs as I
+
+    ctx = make_ctx()
+    for a in range(3):
+        ctx.set_tile(a, 1)
+        ctx.set_segments(a, shape_ctx.get_segments(a))
+        ctx.set_tile(a, shape_ctx.get_tile(a))
+        ctx.set_segment_order(a, shape_ctx.get_segment_order(a))
+    u = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
+    t_end = 1.2 * (args.warmup + args.steps) * ctx.cfl_dt(u, args.cfl)
+    times, prims = I.solar_wind_series(t_end, n_knots=9, seed=11)
+    ctx.set_inflow_series(times, prims)
+    ctx.advance(u, args.warmup, args.cfl)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ctx.advance(u, args.steps, args.cfl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    zones = int(np.prod(setup.U.shape[1:]))
+    return {"value": zones * args.steps / (ms / 1000.0), "unit": "zone-updates/s", "steps": args.steps,
+            "ms_per_step": ms / args.steps, "knots": len(times), "series_span": [0.0, float(t_end)],
+            "simulated_time": ctx.time(u), "status": ctx.status_check(),
+            "finite": bool(torch.isfinite(u).all().item())}
+
+
 def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
     """The learned Riemann guess on the same workload: harvest interface
     records from a plain FP32 run of the start state, train the network on
@@ -239,6 +272,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-series", action="store_true")
     ap.add_argument("--harvest-steps", type=int, default=20)
     ap.add_argument("--harvest-cap", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=3000)
@@ -375,6 +409,10 @@ def main():
         "health": {"status": status, "finite": finite, "floor_hits": st["floor_hits"],
                    "nonconverged": st["nonconverged"], "simulated_time": ctx.time(u)},
     }
+    if not args.no_series:
+        print("[bench] inflow time series", file=sys.stderr, flush=True)
+        out["inflow_series"] = series_leg(args, setup, make_ctx, ctx)
+        torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned"] = learned_leg(args, setup, make_ctx, u, st, value)
         torch.cuda.empty_cache()

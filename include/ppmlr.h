@@ -124,6 +124,17 @@ ppmlr_status ppmlr_set_background(ppmlr_ctx *ctx, const double b_ext[3]);
  * IV-A): primitive rho, vx, vy, vz, Bx, By, Bz (total field), p. */
 ppmlr_status ppmlr_set_inflow(ppmlr_ctx *ctx, const double prim[8]);
 
+/* Time-dependent driving at the inflow faces: n knots (t[k] increasing,
+ * prim[8k..8k+7] as for ppmlr_set_inflow, host arrays, copied).  The inflow
+ * ghost state of a step from t to t + dt is the series at the mid-time
+ * t + dt/2, linear in time between knots and held at the first / last knot
+ * outside them (t = the context's simulated time, see ppmlr_time; a lone
+ * ppmlr_sweep uses t + dt/2 without advancing it).  n = 0 returns to the
+ * constant state of ppmlr_set_inflow.  EINVAL for non-increasing or
+ * non-finite times, non-finite values, or non-positive density or pressure.
+ * Ensembles do not take series.  Synchronises the device. */
+ppmlr_status ppmlr_set_inflow_series(ppmlr_ctx *ctx, int n, const double *t, const double *prim);
+
 /* State the zones inside r_inner are reset to (rest, B' = 0). */
 ppmlr_status ppmlr_set_inner(ppmlr_ctx *ctx, double rho, double p);
 
@@ -135,7 +146,8 @@ ppmlr_status ppmlr_set_inner(ppmlr_ctx *ctx, double rho, double p);
 ppmlr_status ppmlr_sweep(ppmlr_ctx *ctx, const ppmlr_state *state, double dt, int axis);
 
 /* One split step: x, y, z sweeps on even steps and z, y, x on odd steps
- * (step counter held by the context, starts at 0), all with the same dt. */
+ * (step counter held by the context, starts at 0), all with the same dt;
+ * advances the simulated time by dt. */
 ppmlr_status ppmlr_step(ppmlr_ctx *ctx, const ppmlr_state *state, double dt);
 ppmlr_status ppmlr_set_step_index(ppmlr_ctx *ctx, long long step);
 ppmlr_status ppmlr_get_step_index(const ppmlr_ctx *ctx, long long *step);
@@ -148,7 +160,7 @@ ppmlr_status ppmlr_cfl_dt(ppmlr_ctx *ctx, const ppmlr_state *state, double cfl, 
 /* nsteps split steps with dt = cfl-limited and computed on the device from
  * the state at the start of each step (the last sweep of a step fuses the
  * signal-speed maximum); no host synchronisation.  The accumulated simulated
- * time is read with ppmlr_time. */
+ * time (of ppmlr_step and ppmlr_advance) is read with ppmlr_time. */
 ppmlr_status ppmlr_advance(ppmlr_ctx *ctx, const ppmlr_state *state, int nsteps, double cfl);
 ppmlr_status ppmlr_time(ppmlr_ctx *ctx, const ppmlr_state *state, double *t_out);
 

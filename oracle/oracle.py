@@ -205,11 +205,44 @@ class OracleProblem:
         lib().oracle_totals(C.byref(self.p), _dptr(U), _dptr(out))
         return out
 
+    def set_inflow(self, prim) -> None:
+        """Fixed state of the inflow ghosts from now on: rho, vx, vy, vz,
+        Bx, By, Bz (total field), p (Section IV-A upstream conditions)."""
+        for k in range(8):
+            self.p.inflow[k] = float(prim[k])
+
     def dipole(self, r) -> np.ndarray:
         r = np.ascontiguousarray(r, dtype=np.float64)
         out = np.zeros(3)
         lib().oracle_dipole(C.byref(self.p), _dptr(r), _dptr(out))
         return out
+
+
+# ------------------------------------------------- time-dependent driving
+
+def inflow_series_at(times, prims, t):
+    """Inflow state of a time series of upstream conditions at time t.
+
+    The paper drives the upstream face with given solar-wind conditions
+    (Section IV-A); for conditions that vary in time this build reads the
+    series as linear in time between knots, held at the first / last knot
+    outside them, and a step from t to t + dt takes the state at t + dt/2.
+    Written out as that definition: find the knots around t, interpolate."""
+    times = np.asarray(times, dtype=np.float64)
+    prims = np.asarray(prims, dtype=np.float64).reshape(len(times), 8)
+    if t <= times[0]:
+        return prims[0].copy()
+    if t >= times[-1]:
+        return prims[-1].copy()
+    k = int(np.searchsorted(times, t, side="right")) - 1
+    w = (t - times[k]) / (times[k + 1] - times[k])
+    return prims[k] + w * (prims[k + 1] - prims[k])
+
+
+def step_with_series(prob, U, dt, step_index, t, times, prims, stats=None):
+    """One split step from time t with the series' inflow at t + dt/2."""
+    prob.set_inflow(inflow_series_at(times, prims, t + 0.5 * dt))
+    return prob.step(U, dt, step_index, stats)
 
 
 # ---------------------------------------------------------------- unit-level

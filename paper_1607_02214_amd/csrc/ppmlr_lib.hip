@@ -44,6 +44,9 @@ struct ppmlr_ctx {
     unsigned long long *d_cflmax = nullptr;  // signal-speed max (double bits), kCflSlots slots
     double *d_dt = nullptr;                  // device-resident dt
     double *d_time = nullptr;                // accumulated simulated time
+    double *d_series = nullptr;              // inflow time series: rows (t, prim[8])
+    int series_n = 0, series_cap = 0;
+    double *d_inflow = nullptr;              // the current step's inflow from the series (8 values)
     double *d_partials = nullptr;            // totals partial sums
     int partial_blocks = 0;
     long long step = 0;
@@ -300,6 +303,7 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, const T *in, T *u, in
     a.in_vx = (T)c->inflow[1]; a.in_vy = (T)c->inflow[2]; a.in_vz = (T)c->inflow[3];
     a.in_bx = (T)c->inflow[4]; a.in_by = (T)c->inflow[5]; a.in_bz = (T)c->inflow[6];
     a.in_p = (T)c->inflow[7];
+    a.in_dev = c->series_n > 0 ? c->d_inflow : nullptr;
     a.has_inner = c->r_inner > 0.0 ? 1 : 0;
     a.r_inner2 = (T)(c->r_inner * c->r_inner);
     a.inner_rho = (T)c->inner_rho;
@@ -615,8 +619,33 @@ __global__ void clear_slots(unsigned long long *slots)
 
 // dt for the next step from the fused signal-speed maximum; accumulates the
 // simulated time and clears the maximum for the next reduction.
-// (one wave of kCflSlots threads)
-__global__ void dt_kernel(unsigned long long *smax_bits, double *dt, double *t, double cfl)
+// Inflow state of a time series at time t: linear between the knots
+// (rows t_k, prim_k[8], t increasing), held at the first / last knot outside.
+__device__ inline void series_at(const double *series, int n, double t, double *out)
+{
+    int k;
+    double w;
+    if (t <= series[0]) { k = 0; w = 0.0; }
+    else if (t >= series[(size_t)(n - 1) * 9]) { k = n - 1; w = 0.0; }
+    else {
+        int lo = 0, hi = n - 1;                  // series[lo].t <= t < series[hi].t
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (series[(size_t)mid * 9] <= t) lo = mid; else hi = mid;
+        }
+        k = lo;
+        const double t0 = series[(size_t)lo * 9], t1 = series[(size_t)hi * 9];
+        w = (t - t0) / (t1 - t0);
+    }
+    const double *a = series + (size_t)k * 9 + 1;
+    for (int q = 0; q < 8; ++q)
+        out[q] = w == 0.0 ? a[q] : a[q] + w * (a[9 + q] - a[q]);
+}
+
+// (one wave of kCflSlots threads)  A step of length d starting at t takes
+// the inflow of the time series (if any) at its mid-time t + d/2.
+__global__ void dt_kernel(unsigned long long *smax_bits, double *dt, double *t, double cfl, const double *series,
+                          int series_n, double *inflow)
 {
     const unsigned long long bits = slot_max(smax_bits);
     smax_bits[threadIdx.x * ppmlr::kCflStride] = 0ull;
@@ -624,7 +653,16 @@ __global__ void dt_kernel(unsigned long long *smax_bits, double *dt, double *t, 
     double smax = __longlong_as_double((long long)bits);
     double d = smax > 0.0 ? cfl / smax : 0.0;
     *dt = d;
+    if (series_n > 0) series_at(series, series_n, *t + 0.5 * d, inflow);
     *t += d;
+}
+
+// Host-given dt: the time series' inflow at t + dt/2; advance: t += dt.
+__global__ void step_time_kernel(double *t, double dt, int advance, const double *series, int series_n,
+                                 double *inflow)
+{
+    if (series_n > 0) series_at(series, series_n, *t + 0.5 * dt, inflow);
+    if (advance) *t += dt;
 }
 
 __global__ void clear_u64(unsigned long long *p, int n)
@@ -814,6 +852,8 @@ void ppmlr_destroy(ppmlr_ctx *c)
     if (c->d_mlp_frag) (void)hipFree(c->d_mlp_frag);
     if (c->d_pong) (void)hipFree(c->d_pong);
     if (c->d_mlp_theta) (void)hipFree(c->d_mlp_theta);
+    if (c->d_series) (void)hipFree(c->d_series);
+    if (c->d_inflow) (void)hipFree(c->d_inflow);
     free_tables(c);
     delete c;
 }
@@ -891,12 +931,57 @@ ppmlr_status ppmlr_set_inner(ppmlr_ctx *c, double rho, double p)
     return PPMLR_OK;
 }
 
+ppmlr_status ppmlr_set_inflow_series(ppmlr_ctx *c, int n, const double *t, const double *prim)
+{
+    if (!c || n < 0 || n > (1 << 20)) return PPMLR_EINVAL;
+    if (n == 0) {
+        c->series_n = 0;
+        return PPMLR_OK;
+    }
+    if (!t || !prim) return fail(c, PPMLR_EINVAL, "null series");
+    std::vector<double> rows((size_t)n * 9);
+    for (int k = 0; k < n; ++k) {
+        if (!std::isfinite(t[k]) || (k > 0 && !(t[k] > t[k - 1])))
+            return fail(c, PPMLR_EINVAL, "series times must be finite and increasing");
+        for (int q = 0; q < 8; ++q)
+            if (!std::isfinite(prim[(size_t)k * 8 + q])) return fail(c, PPMLR_EINVAL, "series values must be finite");
+        if (!(prim[(size_t)k * 8] > 0.0) || !(prim[(size_t)k * 8 + 7] > 0.0))
+            return fail(c, PPMLR_EINVAL, "series density and pressure must be positive");
+        rows[(size_t)k * 9] = t[k];
+        for (int q = 0; q < 8; ++q) rows[(size_t)k * 9 + 1 + q] = prim[(size_t)k * 8 + q];
+    }
+    // the buffers may be in use by queued work: wait before replacing them
+    ppmlr_status e = hip_check(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (!e && n > c->series_cap) {
+        if (c->d_series) (void)hipFree(c->d_series);
+        c->d_series = nullptr;
+        c->series_cap = 0;
+        e = hip_check(c, hipMalloc((void **)&c->d_series, rows.size() * sizeof(double)), "hipMalloc");
+        if (!e) c->series_cap = n;
+    }
+    if (!e && !c->d_inflow) e = hip_check(c, hipMalloc((void **)&c->d_inflow, 8 * sizeof(double)), "hipMalloc");
+    if (!e) e = hip_check(c, hipMemcpy(c->d_series, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice),
+                          "hipMemcpy");
+    if (e) {
+        c->series_n = 0;
+        return e;
+    }
+    c->series_n = n;
+    // the inflow at the current time until the next step sets it
+    hipLaunchKernelGGL(step_time_kernel, dim3(1), dim3(1), 0, (hipStream_t)0, c->d_time, 0.0, 0, c->d_series,
+                       c->series_n, c->d_inflow);
+    return hip_check(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+}
+
 ppmlr_status ppmlr_sweep(ppmlr_ctx *c, const ppmlr_state *s, double dt, int axis)
 {
     ppmlr_status e = check_state(c, s);
     if (e) return e;
     if (axis < 0 || axis > 2) return fail(c, PPMLR_EINVAL, "axis must be 0, 1 or 2");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, PPMLR_EINVAL, "dt must be positive and finite");
+    if (c->series_n > 0)
+        hipLaunchKernelGGL(step_time_kernel, dim3(1), dim3(1), 0, (hipStream_t)s->stream, c->d_time, dt, 0,
+                           c->d_series, c->series_n, c->d_inflow);
     Flow f{s->u, s->u};
     e = do_sweep(c, s, dt, nullptr, axis, false, f);
     if (e) return e;
@@ -916,6 +1001,8 @@ ppmlr_status ppmlr_step(ppmlr_ctx *c, const ppmlr_state *s, double dt)
     }
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     const int *ord = (c->step % 2 == 0) ? even : odd;
+    hipLaunchKernelGGL(step_time_kernel, dim3(1), dim3(1), 0, (hipStream_t)s->stream, c->d_time, dt, 1, c->d_series,
+                       c->series_n, c->d_inflow);
     Flow f{s->u, s->u};
     for (int k = 0; k < 3; ++k) {
         e = do_sweep(c, s, dt, nullptr, ord[k], false, f);
@@ -971,7 +1058,8 @@ ppmlr_status ppmlr_advance(ppmlr_ctx *c, const ppmlr_state *s, int nsteps, doubl
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     Flow f{s->u, s->u};
     for (int n = 0; n < nsteps; ++n) {
-        hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(ppmlr::kCflSlots), 0, st, c->d_cflmax, c->d_dt, c->d_time, cfl);
+        hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(ppmlr::kCflSlots), 0, st, c->d_cflmax, c->d_dt, c->d_time, cfl,
+                           c->d_series, c->series_n, c->d_inflow);
         const int *ord = (c->step % 2 == 0) ? even : odd;
         for (int k = 0; k < 3; ++k) {
             e = do_sweep(c, s, 0.0, c->d_dt, ord[k], k == 2, f);
@@ -1353,6 +1441,7 @@ ppmlr_status ensemble_check(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         if (states[m]->dtype != states[0]->dtype) return fail(ctxs[0], PPMLR_EINVAL, "members differ in dtype");
         if (states[m]->stream != states[0]->stream) return fail(ctxs[0], PPMLR_EINVAL, "members differ in stream");
         if ((ctxs[m]->step & 1) != (ctxs[0]->step & 1)) return fail(ctxs[0], PPMLR_EINVAL, "step parity differs");
+        if (ctxs[m]->series_n > 0) return fail(ctxs[0], PPMLR_EINVAL, "inflow time series are not supported in ensembles");
         const int elem = states[m]->dtype == PPMLR_F64 ? 8 : 4;
         for (int a = 0; a < 3; ++a)
             if (tile_M(ctxs[m], a, elem) > block)

@@ -134,6 +134,7 @@ struct SweepArgs {
     int has_bd;                 // background field present
     T dip_m, dir_x, dir_y, dir_z, bext_x, bext_y, bext_z;
     T in_rho, in_vx, in_vy, in_vz, in_bx, in_by, in_bz, in_p;   // inflow (total B)
+    const double *in_dev;       // inflow of this step on the device (time series) or nullptr
     T r_inner2, inner_rho, inner_E;
     int has_inner;
     int flatten, janhunen, max_iter;
@@ -467,18 +468,24 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         Q[7] = elem(a.vin[7], o);
     } else if (pen) {
         // inflow ghost: primitive inflow state with B' = B_in - B_d(centre)
+        // (a time series of inflow states puts this step's in a.in_dev)
+        T in[8] = {a.in_rho, a.in_vx, a.in_vy, a.in_vz, a.in_bx, a.in_by, a.in_bz, a.in_p};
+        if (a.in_dev) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) in[k] = (T)a.in_dev[k];
+        }
         T vn, v1, v2, Bn, B1, B2;
-        to_pencil<AX>(a.in_vx, a.in_vy, a.in_vz, vn, v1, v2);
-        to_pencil<AX>(a.in_bx, a.in_by, a.in_bz, Bn, B1, B2);
+        to_pencil<AX>(in[1], in[2], in[3], vn, v1, v2);
+        to_pencil<AX>(in[4], in[5], in[6], Bn, B1, B2);
         T pbn = Bn - bdn, pb1 = B1 - bd1, pb2 = B2 - bd2;
-        Q[0] = a.in_rho;
-        Q[1] = a.in_rho * vn;
-        Q[2] = a.in_rho * v1;
-        Q[3] = a.in_rho * v2;
+        Q[0] = in[0];
+        Q[1] = in[0] * vn;
+        Q[2] = in[0] * v1;
+        Q[3] = in[0] * v2;
         Q[4] = pbn;
         Q[5] = pb1;
         Q[6] = pb2;
-        Q[7] = a.in_p / (gam - T(1)) + T(0.5) * a.in_rho * (vn * vn + v1 * v1 + v2 * v2) +
+        Q[7] = in[7] / (gam - T(1)) + T(0.5) * in[0] * (vn * vn + v1 * v1 + v2 * v2) +
                T(0.5) * (pbn * pbn + pb1 * pb1 + pb2 * pb2);
     } else {
         Q[0] = T(1); Q[1] = Q[2] = Q[3] = T(0); Q[4] = Q[5] = Q[6] = T(0); Q[7] = T(1);

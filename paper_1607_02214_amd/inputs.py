@@ -59,6 +59,22 @@ def solar_wind(n_cc: float, v_kms: float, T_K: float, bz_nT: float, bx_nT=0.0, b
     return np.array([rho, vx, 0.0, 0.0, bx_nT, by_nT, bz_nT, p], dtype=np.float64)
 
 
+def solar_wind_series(t_end: float, n_knots: int = 9, seed: int = 11):
+    """Seeded synthetic upstream time series (no measured solar-wind data is
+    available here): n_knots equally spaced knots on [0, t_end] (code time
+    units) with n ~ logU[3, 10] cm^-3, v ~ U[350, 550] km/s, T = 1e5 K,
+    Bz ~ U[-10, 5] nT, By ~ U[-3, 3] nT.  Returns (times, prims[n, 8])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    times = np.linspace(0.0, t_end, n_knots)
+    n = np.exp(rng.uniform(math.log(3.0), math.log(10.0), n_knots))
+    v = rng.uniform(350.0, 550.0, n_knots)
+    bz = rng.uniform(-10.0, 5.0, n_knots)
+    by = rng.uniform(-3.0, 3.0, n_knots)
+    prims = np.stack([solar_wind(float(n[k]), float(v[k]), 1e5, float(bz[k]), by_nT=float(by[k]))
+                      for k in range(n_knots)])
+    return times, prims
+
+
 # ----------------------------------------------------------------- grids
 
 def uniform_faces(n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:

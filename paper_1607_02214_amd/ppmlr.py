@@ -117,6 +117,7 @@ SIGNATURES = {
     "ppmlr_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "ppmlr_get_tile": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_set_segments": (C.c_int, [_P, C.c_int, C.c_int]),
+    "ppmlr_set_inflow_series": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ppmlr_set_segment_order": (C.c_int, [_P, C.c_int, C.c_int]),
     "ppmlr_get_segment_order": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_get_segments": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
@@ -227,6 +228,17 @@ class Context:
     def set_inflow(self, prim):
         arr = (C.c_double * 8)(*[float(x) for x in prim])
         return self._chk(lib().ppmlr_set_inflow(self.h, arr))
+
+    def set_inflow_series(self, times, prims):
+        """Inflow state as a time series (knot times, [n, 8] primitive
+        states); an empty series returns to the constant inflow."""
+        import numpy as np
+        t = np.ascontiguousarray(times, dtype=np.float64).ravel()
+        p = np.ascontiguousarray(prims, dtype=np.float64).reshape(len(t), 8) if len(t) else np.zeros((0, 8))
+        p = np.ascontiguousarray(p)
+        dp = C.POINTER(C.c_double)
+        return self._chk(lib().ppmlr_set_inflow_series(self.h, len(t), t.ctypes.data_as(dp) if len(t) else None,
+                                                       p.ctypes.data_as(dp) if len(t) else None))
 
     def set_inner(self, rho, p):
         return self._chk(lib().ppmlr_set_inner(self.h, float(rho), float(p)))
