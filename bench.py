@@ -94,7 +94,15 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
         zs += z
         el += e
         chunks += 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = O.get_threads()
+    # the same sample kind on one core (bounded to ~5 s)
+    O.set_threads(1)
+    zs1, el1 = 0, 0.0
+    while el1 < seconds_target / 3.0:
+        z, e = sample(128)
+        zs1 += z
+        el1 += e
+    O.set_threads(threads)
     return {
         "value": zs / el / 3.0,
         "unit": "zone-updates/s",
@@ -102,6 +110,8 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
         "kind": "oracle",
         "sample": f"{chunks} x 2048 random pencils per sweep direction of the 256x192x192 inflow-dipole start "
                   f"state ({zs} zone-sweeps, {el:.1f} s, FP64, OpenMP over pencils); zone-updates = zone-sweeps / 3",
+        "single_core": {"value": zs1 / el1 / 3.0, "unit": "zone-updates/s", "cores": 1,
+                        "sample": f"128-pencil samples, {zs1} zone-sweeps, {el1:.1f} s"},
     }
 
 

@@ -89,6 +89,10 @@ def lib():
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_get_threads.argtypes = []
+        L.oracle_get_threads.restype = C.c_int
         L.oracle_sweep.argtypes = [C.POINTER(Problem), dp, C.c_double, C.c_int, C.POINTER(Stats)]
         L.oracle_sweep.restype = C.c_int
         L.oracle_sweep_pencils.argtypes = [C.POINTER(Problem), dp, C.c_double, C.c_int, C.c_int,
@@ -216,6 +220,15 @@ class OracleProblem:
         out = np.zeros(3)
         lib().oracle_dipole(C.byref(self.p), _dptr(r), _dptr(out))
         return out
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the oracle's pencil loops (timing only)."""
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
 
 
 # ------------------------------------------------- time-dependent driving

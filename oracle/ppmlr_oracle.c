@@ -908,3 +908,14 @@ void oracle_dipole(const oracle_problem *pr, const double r[3], double B[3])
 }
 
 int oracle_ghosts(void) { return NG; }
+
+/* Host threads of the pencil loops (timing only; results do not depend on
+ * it: each pencil is computed by one thread). */
+#ifdef _OPENMP
+#include <omp.h>
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
+#else
+void oracle_set_threads(int n) { (void)n; }
+int oracle_get_threads(void) { return 1; }
+#endif
