@@ -40,11 +40,18 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the HIP sources with comments and whitespace removed (a
+    comment edit does not make the committed counters stale; any code edit
+    does)."""
+    import re
     h = hashlib.sha256()
     for rel in ("paper_1607_02214_amd/csrc/ppmlr_sweep.hpp", "paper_1607_02214_amd/csrc/ppmlr_mlp.hpp",
                 "paper_1607_02214_amd/csrc/ppmlr_lib.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

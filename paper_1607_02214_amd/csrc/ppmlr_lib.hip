@@ -205,13 +205,12 @@ int seg_fast_for(const ppmlr_ctx *c, int axis)
 // Zones of one tile's pencil segment (interior + ghosts).
 int tile_M(const ppmlr_ctx *c, int axis, int elem) { return seg_len(c->n[axis], seg_count(c, axis, elem)) + 2 * kG; }
 
-// Automatic tile: the number of pencils per workgroup that wastes the fewest
-// lanes (padding to whole waves plus ghost zones), within the thread budget.
 // LDS stride of a sweep launch with `threads` lanes: the smallest of the
 // compile-time strides 256, 384, ..., 1024 (steps of 128) that holds them and
-// whose two buffers fit the 160 KB LDS; 0 = the exact runtime stride (FP64
-// tiles above 896 lanes); -1 = does not fit.  A stride close to the
-// workgroup size leaves LDS for more resident workgroups per CU.
+// whose two buffers fit the 160 KB LDS; 0 = the exact runtime stride (an
+// FP64 tile of 832 lanes, whose rounded stride would not fit); -1 = does not
+// fit.  A stride close to the workgroup size leaves LDS for more resident
+// workgroups per CU.
 int stride_for(int threads, int elem)
 {
     if (threads > 1024) return -1;
@@ -221,9 +220,12 @@ int stride_for(int threads, int elem)
     return -1;
 }
 
+// Automatic tile: the number of pencil segments per workgroup that wastes the
+// fewest lanes (padding to whole waves plus ghost zones), within the thread
+// budget.
 int auto_tile(const ppmlr_ctx *c, int axis, int elem)
 {
-    const int N = seg_len(c->n[axis], seg_count(c, axis, elem)), M = N + 2 * kG;
+    const int L = seg_len(c->n[axis], seg_count(c, axis, elem)), M = L + 2 * kG;
     const int cap = (elem == 8) ? 512 : 1024;
     const int nq = (axis == 0) ? c->n[1] : c->n[0];
     int best = 1;
@@ -233,7 +235,7 @@ int auto_tile(const ppmlr_ctx *c, int axis, int elem)
         if (thr > cap && P > 1) break;
         if (stride_for(block_threads(P, M), elem) < 0) break;
         int tiles_q = (nq + P - 1) / P;
-        double cost = (double)thr * tiles_q / ((double)N * nq);  // lanes per useful zone
+        double cost = (double)thr * tiles_q / ((double)L * nq);  // lanes per useful zone
         if (cost < best_cost - 1e-9) { best_cost = cost; best = P; }
     }
     return best;
