@@ -614,19 +614,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         T c1_ = avgR(pLc[4], pDc[4], p6c[4], yn);
         T c2_ = avgR(pLc[5], pDc[5], p6c[5], yn);
         T T1 = bf1 + c1_, T2 = bf2 + c2_;
-        T C = Ar<T>::sqrt_(r_ * (gam * p_ + T1 * T1 + T2 * T2));
+        const T C2 = r_ * (gam * p_ + T1 * T1 + T2 * T2);
+        T C = Ar<T>::sqrt_(C2);
         T P0 = p_ + T(0.5) * (T1 * T1 + T2 * T2);
         T Pd = T(0.5) * (bf1 * bf1 + bf2 * bf2);
         T Pt_ = p_ + bf1 * c1_ + bf2 * c2_ + T(0.5) * (c1_ * c1_ + c2_ * c2_) + corrP;
         if (Pt_ + Pd < T(0.5) * P0) Pt_ = T(0.5) * P0 - Pd;
-        T ge = C * C * Ar<T>::rcp(r_ * (Pt_ + Pd));
+        // k = (ge + 1) / (2 ge) with ge = C^2 / (rho P): 1/2 + rho P / (2 C^2)
+        const T kh = T(0.5) * r_ * (Pt_ + Pd) * Ar<T>::rcp(C2) + T(0.5);
         LPt = Pt_;
         LrN = r_;
         LT1 = T1;
         LT2 = T2;
         Lu = u_ + corrU;
         LC = C;
-        Lk = (ge + T(1)) * Ar<T>::rcp(T(2) * ge);
+        Lk = kh;
         Lr = Ar<T>::sqrt_(avgR(pLc[0], pDc[0], p6c[0], yA));
         Lv1 = avgR(pLc[2], pDc[2], p6c[2], yA) + corrV1;
         Lv2 = avgR(pLc[3], pDc[3], p6c[3], yA) + corrV2;
@@ -641,17 +643,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         T c1_ = avgL(pLc[4], pDc[4], p6c[4], yn);
         T c2_ = avgL(pLc[5], pDc[5], p6c[5], yn);
         T T1 = bl1 + c1_, T2 = bl2 + c2_;
-        T C = Ar<T>::sqrt_(r_ * (gam * p_ + T1 * T1 + T2 * T2));
+        const T C2 = r_ * (gam * p_ + T1 * T1 + T2 * T2);
+        T C = Ar<T>::sqrt_(C2);
         T P0 = p_ + T(0.5) * (T1 * T1 + T2 * T2);
         T Pd = T(0.5) * (bl1 * bl1 + bl2 * bl2);
         T Pt_ = p_ + bl1 * c1_ + bl2 * c2_ + T(0.5) * (c1_ * c1_ + c2_ * c2_) + corrP;
         if (Pt_ + Pd < T(0.5) * P0) Pt_ = T(0.5) * P0 - Pd;
-        T ge = C * C * Ar<T>::rcp(r_ * (Pt_ + Pd));
+        // k = (ge + 1) / (2 ge) with ge = C^2 / (rho P): 1/2 + rho P / (2 C^2)
+        const T kh = T(0.5) * r_ * (Pt_ + Pd) * Ar<T>::rcp(C2) + T(0.5);
         if (slot_ok) {
             sA[0 * S + tid] = Pt_;
             sA[1 * S + tid] = u_ + corrU;
             sA[2 * S + tid] = C;
-            sA[3 * S + tid] = (ge + T(1)) * Ar<T>::rcp(T(2) * ge);
+            sA[3 * S + tid] = kh;
             sA[4 * S + tid] = Ar<T>::sqrt_(avgL(pLc[0], pDc[0], p6c[0], yA));
             sA[5 * S + tid] = avgL(pLc[2], pDc[2], p6c[2], yA) + corrV1;
             sA[6 * S + tid] = avgL(pLc[3], pDc[3], p6c[3], yA) + corrV2;
