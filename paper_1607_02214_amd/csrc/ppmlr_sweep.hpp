@@ -318,7 +318,12 @@ __device__ inline void wave_add(unsigned int *s_ctr, bool pred)
 }
 __device__ inline void wave_hist(unsigned int *s_hist, bool counted, int bin)
 {
-    unsigned long long active = __ballot(counted);
+    // bin 0 (a face whose linear guess already meets the tolerance) is by far
+    // the most common: one ballot for it, then a loop over the other bins
+    const unsigned long long zero = __ballot(counted && bin == 0);
+    if (zero != 0ull && __lane_id() == __ffsll((long long)zero) - 1)
+        atomicAdd(&s_hist[0], (unsigned int)__popcll(zero));
+    unsigned long long active = __ballot(counted && bin != 0);
     while (active) {
         int leader = __ffsll((long long)active) - 1;
         int lb = __shfl(bin, leader);
