@@ -61,7 +61,8 @@ typedef struct {
     double tol_f64;     /* Newton stop |dP| <= tol P in FP64, 1e-12 */
     double tol_f32;     /* same in FP32, 1e-6 */
     double p_floor;     /* thermal-pressure floor (absolute), 1e-8 */
-    int collect_stats;  /* iteration histogram and floor counters, 1 */
+    int collect_stats;  /* iteration histogram and floor counters, 1 (about
+                           2 % of a sweep's time) */
     int debug_cfl;      /* ppmlr_step checks dt against the CFL limit, 0 */
 } ppmlr_options;
 
@@ -86,7 +87,9 @@ typedef struct {
     void *stream;       /* hipStream_t; NULL = default stream */
 } ppmlr_state;
 
-/* Counters accumulated since the last ppmlr_reset_stats. */
+/* Counters accumulated since the last ppmlr_reset_stats.  Interface counts
+ * cover the faces -1/2 .. N-1/2 of every pencil, each once whatever the
+ * segments. */
 typedef struct {
     long long iters_hist[32];  /* Newton iterations per interface (bin 31: >=31) */
     long long floor_hits;      /* zones whose pressure was floored */
