@@ -237,9 +237,9 @@ def inflow_series_at(times, prims, t):
     """Inflow state of a time series of upstream conditions at time t.
 
     The paper drives the upstream face with given solar-wind conditions
-    (Section IV-A); for conditions that vary in time this build reads the
-    series as linear in time between knots, held at the first / last knot
-    outside them, and a step from t to t + dt takes the state at t + dt/2.
+    (Section IV-A); conditions that vary in time are read here as linear in
+    time between knots, held at the first / last knot outside them, and a
+    step from t to t + dt takes the state at t + dt/2.
     Written out as that definition: find the knots around t, interpolate."""
     times = np.asarray(times, dtype=np.float64)
     prims = np.asarray(prims, dtype=np.float64).reshape(len(times), 8)
