@@ -31,12 +31,12 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (packed); 78.6 without pa
 FP32_UNPACKED_TFLOPS = 78.6
 # FP32 operations per zone-sweep: adds + multiplies + transcendentals + 2 x
 # fused multiply-adds per lane, from the SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F32
-# counters of the sweep kernels on this workload (x 1203, y 1120, z 1130;
+# counters of the sweep kernels on this workload (x 1203, y 1124, z 1138;
 # the smallest is used; ghost zones of pencil segments are not counted; the
 # Newton loop runs to each wave's slowest lane, so the figure moves by ~1 %
 # with the tile shape).  The committed counter summary's own figure is used
 # when it was taken from the current kernel source.
-FLOPS_PER_ZONE_SWEEP = 1120.0
+FLOPS_PER_ZONE_SWEEP = 1124.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 

@@ -215,8 +215,8 @@ int stride_for(int threads, int elem)
 {
     if (threads > 1024) return -1;
     const int sm = threads <= 256 ? 256 : (threads + 127) / 128 * 128;
-    if ((size_t)(kSlotsA + kSlotsB) * sm * elem <= 160 * 1024) return sm;
-    if ((size_t)(kSlotsA + kSlotsB) * threads * elem <= 160 * 1024 && elem == 8) return 0;
+    if (ppmlr::lds_bytes(kSlotsA + kSlotsB, sm, elem) <= 160 * 1024) return sm;
+    if (ppmlr::lds_bytes(kSlotsA + kSlotsB, threads, elem) <= 160 * 1024 && elem == 8) return 0;
     return -1;
 }
 
@@ -341,7 +341,7 @@ ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t 
 {
     const int threads = block_threads(a.P, a.M);
     const int slots = (GUESS == ppmlr::kGuessPlain ? kSlotsA : ppmlr::kSlotsAGuess) + kSlotsB;
-    const size_t lds = (size_t)slots * (SM > 0 ? SM : a.S) * sizeof(T);
+    const size_t lds = ppmlr::lds_bytes(slots, SM > 0 ? SM : a.S, (int)sizeof(T));
     const int blocks = 8 * a.tiles_per_xcd;
     auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM, GUESS>;
     if (lds > 64 * 1024) {
@@ -406,7 +406,7 @@ ppmlr_status sweep_typed(ppmlr_ctx *c, const T *in, T *u, hipStream_t st, double
 {
     const int P = pick_tile(c, axis, (int)sizeof(T));
     const int M = tile_M(c, axis, (int)sizeof(T));
-    if (block_threads(P, M) > 1024 || (size_t)(kSlotsA + kSlotsB) * P * M * sizeof(T) > 160 * 1024)
+    if (block_threads(P, M) > 1024 || ppmlr::lds_bytes(kSlotsA + kSlotsB, P * M, (int)sizeof(T)) > 160 * 1024)
         return fail(c, PPMLR_EINVAL, "tile does not fit one workgroup");
     ppmlr::SweepArgs<T> a;
     fill_args(c, a, in, u, axis, dt, dt_dev, P, seg_count(c, axis, (int)sizeof(T)));
@@ -1149,7 +1149,7 @@ ppmlr_status ppmlr_set_tile(ppmlr_ctx *c, int axis, int pencils)
     if (pencils > 0) {
         int M = tile_M(c, axis, 4);
         if (block_threads(pencils, M) > 1024) return fail(c, PPMLR_EINVAL, "tile exceeds 1024 threads");
-        if ((size_t)(kSlotsA + kSlotsB) * pencils * M * 4 > 160 * 1024)
+        if (ppmlr::lds_bytes(kSlotsA + kSlotsB, pencils * M, 4) > 160 * 1024)
             return fail(c, PPMLR_EINVAL, "tile exceeds the LDS budget");
     }
     c->tile[axis] = pencils;
@@ -1377,7 +1377,7 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
     }
     // signal-speed maximum of every member's current state
     for (int m = 0; m < n && !err; ++m) err = cfl_launch(ctxs[m], states[m]);
-    const size_t lds = (size_t)(kSlotsA + kSlotsB) * block * sizeof(T);
+    const size_t lds = ppmlr::lds_bytes(kSlotsA + kSlotsB, block, (int)sizeof(T));
     static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     long long j = 0;                                       // sweeps enqueued by this call
     for (int s = 0; s < steps && !err; ++s) {

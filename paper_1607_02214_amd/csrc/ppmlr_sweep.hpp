@@ -31,21 +31,38 @@ namespace ppmlr {
 constexpr int kG = 7;           // ghost zones per side
 constexpr int kSlotsA = 16;     // values per zone in LDS buffer A
 constexpr int kSlotsAGuess = 19;  // buffer A of the learned / harvest sweeps (3 more face values)
-constexpr int kSlotsB = 8;
+constexpr int kSlotsB = 8;       // values per zone in LDS buffer B
 // The signal-speed maximum is accumulated in kCflSlots words kCflStride
 // words apart (workgroup b uses slot b mod kCflSlots), so that the
 // workgroups' atomics do not all queue on one address; readers take the
 // maximum of the slots.
 constexpr int kCflSlots = 64;
-constexpr int kCflStride = 32;      // values per zone in LDS buffer B
+constexpr int kCflStride = 32;
 constexpr int kStatWords = 37;  // iteration histogram [32], floors, nonconverged, nonphys,
                                 // learned-guess faces, learned-guess fallbacks
 constexpr int kStatSlots = 64;  // copies of the counters (workgroup b adds to copy b % 64)
 
+// Dynamic LDS of a sweep workgroup: the tile buffers A and B (slots values
+// per zone, stride S) from address 0, then the workgroup's scalars: 16
+// doubles of per-wave signal-speed maxima, the kStatWords counters and the
+// learned guess's face count.  With the buffers at address 0 a zone's LDS
+// address is its lane offset, with the slot in the instruction's offset
+// field; behind static shared arrays every address needed their size added.
+constexpr int kLdsTail = 16 * 8 + (kStatWords + 1) * 4;
+__host__ __device__ constexpr size_t lds_tile_bytes(int slots, int S, int elem)
+{
+    return ((size_t)slots * (size_t)S * (size_t)elem + 15) / 16 * 16;
+}
+__host__ __device__ constexpr size_t lds_bytes(int slots, int S, int elem)
+{
+    return lds_tile_bytes(slots, S, elem) + kLdsTail;
+}
+
 enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
 
-// Arithmetic helpers: FP64 uses IEEE division and square root, FP32 the
-// hardware reciprocal / square-root approximations (1 ulp).
+// Arithmetic helpers: FP64 uses Newton-refined reciprocals and reciprocal
+// square roots and the IEEE square root, FP32 the hardware reciprocal /
+// square-root approximations (1 ulp).
 template <typename T> struct Ar;
 // FP64: the hardware reciprocal and reciprocal square root refined by two
 // Newton steps each (quadratic convergence: faithfully rounded results for
@@ -1070,9 +1087,11 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024)
     __attribute__((amdgpu_waves_per_eu(GUESS == kGuessLearned ? 4 : 1))) sweep_kernel(const SweepArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double s_red[16];
-    __shared__ unsigned int s_stat[kStatWords];
-    __shared__ unsigned int s_guess[1];
+    constexpr int kSlots = (GUESS == kGuessPlain ? kSlotsA : kSlotsAGuess) + kSlotsB;
+    unsigned char *tail = smem_raw + lds_tile_bytes(kSlots, SM > 0 ? SM : a.S, (int)sizeof(T));
+    double *s_red = reinterpret_cast<double *>(tail);
+    unsigned int *s_stat = reinterpret_cast<unsigned int *>(tail + 16 * sizeof(double));
+    unsigned int *s_guess = s_stat + kStatWords;
     // XCD-aware tile order: consecutive workgroups go to different XCDs
     // round-robin, so workgroups b, b+8, b+16, ... (one XCD) take consecutive
     // tiles (q fastest, then r) and share L2 lines of neighbouring pencils.
@@ -1114,8 +1133,6 @@ template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM>
 __global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepArgs<T> e)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double s_red[16];
-    __shared__ unsigned int s_stat[kStatWords];
     const int b = blockIdx.x;
     const int j = (b & 7) * e.per_xcd + (b >> 3);
     if (j >= e.total) return;
@@ -1125,6 +1142,9 @@ __global__ void __launch_bounds__(SM) ensemble_sweep_kernel(const EnsembleSweepA
         if (e.mo[mid] <= j) lo = mid; else hi = mid - 1;
     }
     const SweepArgs<T> &a = e.desc[lo];
+    unsigned char *tail = smem_raw + lds_tile_bytes(kSlotsA + kSlotsB, SM, (int)sizeof(T));
+    double *s_red = reinterpret_cast<double *>(tail);
+    unsigned int *s_stat = reinterpret_cast<unsigned int *>(tail + 16 * sizeof(double));
     const int t = j - e.mo[lo];
     int seg, tt;                                  // as in the single-run order
     if (a.seg_fast) { seg = t % a.nseg; tt = t / a.nseg; }
