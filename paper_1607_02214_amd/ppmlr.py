@@ -6,7 +6,8 @@ PyTorch provides device memory and streams: a state is a contiguous CUDA
 (rho, m_x, m_y, m_z, B'_x, B'_y, B'_z, E').
 
 The library must be built (``python -m paper_1607_02214_amd.build`` or
-``__graft_entry__.build()``); importing this module without it raises.
+``__graft_entry__.build()``); without it the first call into the library
+raises ImportError (there is no fallback path).
 """
 from __future__ import annotations
 
