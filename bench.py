@@ -111,6 +111,14 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
         zs1 += z
         el1 += e
     O.set_threads(threads)
+    # the small periodic case in full: 32^3 zones, 20 FP64 steps at CFL 0.4
+    from paper_1607_02214_amd import inputs as I
+    U1, faces1 = I.c1_state(n=32)
+    prob1 = O.OracleProblem(faces1)
+    t0 = time.perf_counter()
+    for s in range(20):
+        U1 = prob1.step(U1, prob1.cfl_dt(U1, 0.4), s)
+    el_c1 = time.perf_counter() - t0
     return {
         "value": zs / el / 3.0,
         "unit": "zone-updates/s",
@@ -120,6 +128,9 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
                   f"state ({zs} zone-sweeps, {el:.1f} s, FP64, OpenMP over pencils); zone-updates = zone-sweeps / 3",
         "single_core": {"value": zs1 / el1 / 3.0, "unit": "zone-updates/s", "cores": 1,
                         "sample": f"128-pencil samples, {zs1} zone-sweeps, {el1:.1f} s"},
+        "periodic_32cubed_full": {"value": 32 ** 3 * 20 / el_c1, "unit": "zone-updates/s", "cores": threads,
+                                  "sample": f"32^3 periodic box, 20 whole FP64 steps with the CFL 0.4 dt "
+                                            f"({el_c1:.2f} s)"},
     }
 
 
