@@ -195,9 +195,9 @@ def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
     ctx = make_ctx()
     ctx.set_guess(ppmlr.GUESS_LEARNED, theta)
     u = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
-    tiles = ctx.autotune(u, reps=3)
-    ctx.advance(u, args.warmup, args.cfl)
+    ctx.advance(u, args.warmup, args.cfl)      # warm-up, then the tile search on that flow
     torch.cuda.synchronize()
+    tiles = ctx.autotune(u, reps=5)
     ctx.reset_stats()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()

@@ -8,10 +8,22 @@ from . import inputs
 from . import ppmlr
 
 
+def canonical_order(records):
+    """The rows of a record buffer in lexicographic order of their values
+    (first column most significant).  The waves of a sweep append records in
+    an order that depends on their scheduling; this order depends on the
+    record set only, so that training on it is reproducible."""
+    import torch
+    perm = torch.arange(records.shape[0], device=records.device)
+    for c in range(records.shape[1] - 1, -1, -1):       # least significant first, stable
+        perm = perm[torch.sort(records[perm, c], stable=True).indices]
+    return records[perm]
+
+
 def harvest(ctx, u, steps, cfl, capacity, stream=None):
     """Advance `u` by `steps` steps with the plain guess while every selected
-    face appends a record; returns (records [n, 28] device tensor, number of
-    records offered)."""
+    face appends a record; returns (records [n, 28] device tensor in
+    canonical order, number of records offered)."""
     import torch
     rec = torch.empty((int(capacity), ppmlr.RECORD_FLOATS), dtype=torch.float32, device=u.device)
     cnt = torch.zeros(1, dtype=torch.int64, device=u.device)
@@ -23,18 +35,22 @@ def harvest(ctx, u, steps, cfl, capacity, stream=None):
     finally:
         ctx.set_guess(ppmlr.GUESS_PLAIN, stream=stream)
         ctx.set_harvest(None)
-    return rec[:min(offered, int(capacity))], offered
+    return canonical_order(rec[:min(offered, int(capacity))]), offered
 
 
 def train(records, steps, batch=4096, lr=1e-3, seed=0, log_every=0, log=None):
     """Adam on the mean-squared error of the two targets over consecutive
-    batches of the record buffer (cycled); returns (theta, [(step, loss)])."""
+    batches (cycled) of a permutation of the records drawn from `seed`, which
+    also seeds the initial parameters; returns (theta, [(step, loss)])."""
     import torch
     n = int(records.shape[0])
     if n < 1:
         raise ValueError("no records to train on")
     batch = min(int(batch), n)
     theta = torch.from_numpy(inputs.mlp_init(seed)).to(records.device)
+    gen = torch.Generator(device=records.device)
+    gen.manual_seed(int(seed))
+    records = records[torch.randperm(n, generator=gen, device=records.device)]
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
     mlp = ppmlr.MLP(batch)
