@@ -196,7 +196,7 @@ ppmlr_status ppmlr_get_tile(const ppmlr_ctx *ctx, int axis, int dtype, int *penc
  * tile then holds `pencils` pencil segments of ceil(N / segments) interior
  * zones (the last segment takes the rest) plus the 7 ghost zones on either
  * side that the reconstruction, Riemann solve and remap of the sweep
- * (Section II-B) reach: neighbouring segments overlap by those ghosts and
+ * (Section II, the method) reach: neighbouring segments overlap by those ghosts and
  * each zone is computed by its own segment only, so the result does not
  * depend on the segment count, bit for bit.  Shorter tiles trade recomputed
  * ghost zones for fewer state planes per workgroup; the z sweep of a large

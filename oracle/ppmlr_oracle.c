@@ -42,7 +42,12 @@
  * (along an axis, oblique, on a moving background, with the background field
  * carried as B_d); Sod and colliding-stream problems against the exact
  * solution; convergence of the dipole split form to the plain form; the
- * -v div B' source; inflow ghosts and the inner-boundary reset.
+ * -v div B' source; inflow ghosts and the inner-boundary reset; the CFL dt
+ * against the largest eigenvalue of the MHD Jacobian per axis (total field,
+ * stretched grids, inner mask); the totals against closed-form volume
+ * integrals of linear fields; the Alfven pair with unequal densities against
+ * the two-medium jump conditions; the factor 2 of the Eq. 1.8 limiter (a
+ * clipped linear profile reaches the neighbouring average).
  *
  * Parity unpinned (no check sees them): the time-centring term
  * B'_n dB_d,t/dm (its effect stays below the truncation error of every
