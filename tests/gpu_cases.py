@@ -104,6 +104,18 @@ def normwise_errors(gpu: np.ndarray, ref: np.ndarray):
     return np.max(np.abs(g - r), axis=1) / scale
 
 
+def pointwise_errors(gpu: np.ndarray, ref: np.ndarray, floor: float = 1e-6):
+    """Per conserved variable: max_i |gpu_i - ref_i| / max(|ref_i|, floor *
+    max |ref|), the pointwise form of the error metric (each zone against its
+    own magnitude, so that a small-valued region is not measured against the
+    largest value elsewhere in the box)."""
+    g = gpu.reshape(8, -1).astype(np.float64)
+    r = ref.reshape(8, -1).astype(np.float64)
+    scale = np.maximum(np.max(np.abs(r), axis=1), 1e-300)
+    den = np.maximum(np.abs(r), floor * scale[:, None])
+    return np.max(np.abs(g - r) / den, axis=1)
+
+
 def log(msg):
     print(msg, flush=True)
     sys.stdout.flush()
