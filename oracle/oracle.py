@@ -58,6 +58,7 @@ class Problem(C.Structure):
         ("max_iter", C.c_int),
         ("tol", C.c_double),
         ("p_floor", C.c_double),
+        ("tracing", C.c_int),
     ]
 
 
@@ -115,6 +116,12 @@ def lib():
         L.oracle_riemann_alfven.argtypes = [C.c_double] * 7 + [dp, dp]
         L.oracle_dipole.argtypes = [C.POINTER(Problem), dp, dp]
         L.oracle_ghosts.restype = C.c_int
+        L.oracle_mhd7_eigen.argtypes = [C.c_double] * 6 + [dp, dp]
+        L.oracle_mhd7_eigen.restype = None
+        L.oracle_trace7.argtypes = [C.c_double] * 6 + [dp, C.c_double, C.c_double, dp, dp]
+        L.oracle_trace7.restype = C.c_int
+        L.oracle_riemann7.argtypes = [dp, dp] + [C.c_double] * 4 + [dp]
+        L.oracle_riemann7.restype = C.c_int
         L.mlp_gelu.argtypes = [C.c_double]
         L.mlp_gelu.restype = C.c_double
         L.mlp_gelu_grad.argtypes = [C.c_double]
@@ -139,7 +146,7 @@ class OracleProblem:
     def __init__(self, faces, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), gamma=5.0 / 3.0,
                  dip_moment=0.0, dip_dir=(0.0, 0.0, -1.0), bext=(0.0, 0.0, 0.0), inflow=None, r_inner=0.0,
                  inner_rho=1.0, inner_p=1.0, flatten=True, janhunen=True, max_iter=20,
-                 tol=1e-12, p_floor=1e-8):
+                 tol=1e-12, p_floor=1e-8, tracing=0):
         self.faces = [np.ascontiguousarray(f, dtype=np.float64) for f in faces]
         p = Problem()
         for a in range(3):
@@ -163,6 +170,7 @@ class OracleProblem:
         p.max_iter = int(max_iter)
         p.tol = tol
         p.p_floor = p_floor
+        p.tracing = int(tracing)
         self.p = p
 
     @property
@@ -300,6 +308,39 @@ def flattening(Pt, Pa, un):
     f = np.zeros_like(Pt)
     lib().oracle_flattening(len(Pt), _dptr(Pt), _dptr(Pa), _dptr(un), _dptr(f))
     return f
+
+
+def mhd7_eigen(rho, p, gamma, Bn, Bt1, Bt2):
+    """Eigenvalues (order -f, -A, -s, 0, +s, +A, +f) and right eigenvectors
+    (columns) of the Lagrangian 1D MHD system in the primitive variables
+    (rho, u, v_t1, v_t2, B_t1, B_t2, p) at a state (total field)."""
+    lam = np.zeros(7)
+    R = np.zeros(49)
+    lib().oracle_mhd7_eigen(rho, p, gamma, Bn, Bt1, Bt2, _dptr(lam), _dptr(R))
+    return lam, R.reshape(7, 7)
+
+
+def trace7(rho, p, gamma, Bn, Bt1, Bt2, par, dt, dm):
+    """Face states (right face, left face) of one zone by full
+    characteristic tracing; par[7][3] = (aL, dA, a6) per primitive; the
+    eigen-structure at (rho, p, Bn, Bt1, Bt2)."""
+    par = np.ascontiguousarray(par, dtype=np.float64).reshape(21)
+    WL = np.zeros(7)
+    WR = np.zeros(7)
+    if lib().oracle_trace7(rho, p, gamma, Bn, Bt1, Bt2, _dptr(par), dt, dm, _dptr(WL), _dptr(WR)) != 0:
+        raise ValueError("singular eigenvector matrix")
+    return WL, WR
+
+
+def riemann7(WL, WR, gamma, Bn, Bd1=0.0, Bd2=0.0):
+    """Face state of the linearised seven-wave Riemann problem (characteristic
+    mode) between primitive states W_L, W_R (B'_t components)."""
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    Ws = np.zeros(7)
+    if lib().oracle_riemann7(_dptr(WL), _dptr(WR), gamma, Bn, Bd1, Bd2, _dptr(Ws)) != 0:
+        raise ValueError("singular eigenvector matrix")
+    return Ws
 
 
 def riemann_normal(PtL, PtR, Pd, uL, uR, CL, CR, gL, gR, tol=1e-12, max_iter=20):

@@ -81,6 +81,12 @@ typedef struct {
     int max_iter;
     double tol;               /* Newton stop: |dP| <= tol * P */
     double p_floor;           /* thermal-pressure floor (absolute) */
+    int tracing;              /* 0: two-family tracing (fast pair, Alfven pair)
+                                 with the oblique coupling terms and the
+                                 two-shock / linear Alfven solvers; 1:
+                                 characteristic mode: tracing of the seven
+                                 waves and the linearised seven-wave
+                                 Riemann problem */
 } oracle_problem;
 
 typedef struct {
@@ -194,6 +200,176 @@ static double par_avg_right_part(double aL, double dA, double a6, double y)
 static double par_avg_left_part(double aL, double dA, double a6, double y)
 {
     return aL + 0.5 * y * (dA + (1.0 - (2.0 / 3.0) * y) * a6);
+}
+
+/* ------------------------------------------------------------------ */
+/* Full characteristic tracing: the seven waves of Lagrangian 1D MHD    */
+/* ------------------------------------------------------------------ */
+
+/* Eigen-structure of the 1D ideal-MHD equations in the mass coordinate m,
+ * in the primitive variables W = (rho, u, v_t1, v_t2, B_t1, B_t2, p) of a
+ * pencil: dW/dt + A dW/dm = 0, where A is rho times the Eulerian primitive
+ * matrix without the advection term (the material derivative takes the flow
+ * along), so the eigenvectors are the Eulerian ones and the eigenvalues are
+ * rho times the wave speeds relative to the flow.  Order of the waves:
+ * 0 -fast, 1 -Alfven, 2 -slow, 3 entropy, 4 +slow, 5 +Alfven, 6 +fast.
+ * Right eigenvectors (columns of R) in the normalisation of Roe & Balsara
+ * (1996): weights alpha_f^2 = (a^2 - c_s^2)/(c_f^2 - c_s^2) and alpha_s^2 =
+ * (c_f^2 - a^2)/(c_f^2 - c_s^2) (1 and 0 where c_f = c_s), the unit vector
+ * beta along the transverse field (a fixed diagonal direction where the
+ * transverse field vanishes) and sgn(B_n) with sgn(0) = 1, so that the set
+ * stays complete at every degeneracy.  Bn, Bt1, Bt2: the total field. */
+static void mhd7_eigen(double rho, double p, double g, double Bn, double Bt1, double Bt2,
+                       double lam[7], double R[7][7])
+{
+    double a2 = g * p / rho;
+    double bn2 = Bn * Bn / rho;
+    double bt2 = (Bt1 * Bt1 + Bt2 * Bt2) / rho;
+    double bt = sqrt(Bt1 * Bt1 + Bt2 * Bt2);
+    double b2 = bn2 + bt2;
+    /* c_f^2 - c_s^2, written without cancellation: exact where bt = 0 */
+    double disc = sqrt((a2 - b2) * (a2 - b2) + 4.0 * a2 * bt2);
+    double cf2 = 0.5 * (a2 + b2 + disc);
+    double cs2 = cf2 > 0.0 ? a2 * bn2 / cf2 : 0.0;   /* c_f^2 c_s^2 = a^2 c_A^2 */
+    double cf = sqrt(cf2), cs = sqrt(cs2), ca = sqrt(bn2), a = sqrt(a2);
+    /* alpha_f^2 = (a^2 - c_s^2) / (c_f^2 - c_s^2) = (1 + (a^2 - b^2) / disc) / 2
+     * and alpha_s^2 = 1 - alpha_f^2; the smaller of the two is written as
+     * 2 a^2 bt^2 / (disc (disc + |a^2 - b^2|)), exact for small bt */
+    double af, as;
+    if (disc > 0.0) {
+        double small = 2.0 * a2 * bt2 / (disc * (disc + fabs(a2 - b2)));
+        if (a2 >= b2) { as = sqrt(dmin(1.0, small)); af = sqrt(dmax(0.0, 1.0 - small)); }
+        else { af = sqrt(dmin(1.0, small)); as = sqrt(dmax(0.0, 1.0 - small)); }
+    } else {                                          /* a = c_A, no transverse field */
+        af = 1.0;
+        as = 0.0;
+    }
+    double be1, be2;
+    if (bt > 1e-12 * sqrt(rho * (a2 + b2))) { be1 = Bt1 / bt; be2 = Bt2 / bt; }
+    else { be1 = be2 = sqrt(0.5); }
+    double sg = Bn < 0.0 ? -1.0 : 1.0;
+    double sr = sqrt(rho);
+    for (int i = 0; i < 7; ++i)
+        for (int k = 0; k < 7; ++k) R[i][k] = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        double s = side == 0 ? -1.0 : 1.0;          /* direction of the wave */
+        int kf = side == 0 ? 0 : 6, ka = side == 0 ? 1 : 5, ks = side == 0 ? 2 : 4;
+        lam[kf] = s * rho * cf;
+        lam[ka] = s * rho * ca;
+        lam[ks] = s * rho * cs;
+        /* fast */
+        R[0][kf] = rho * af;
+        R[1][kf] = s * af * cf;
+        R[2][kf] = -s * as * cs * sg * be1;
+        R[3][kf] = -s * as * cs * sg * be2;
+        R[4][kf] = as * sr * a * be1;
+        R[5][kf] = as * sr * a * be2;
+        R[6][kf] = af * rho * a2;
+        /* slow */
+        R[0][ks] = rho * as;
+        R[1][ks] = s * as * cs;
+        R[2][ks] = s * af * cf * sg * be1;
+        R[3][ks] = s * af * cf * sg * be2;
+        R[4][ks] = -af * sr * a * be1;
+        R[5][ks] = -af * sr * a * be2;
+        R[6][ks] = as * rho * a2;
+        /* Alfven: the velocity and field across beta, dB = -s sgn(Bn) sqrt(rho) dv */
+        R[2][ka] = -be2;
+        R[3][ka] = be1;
+        R[4][ka] = s * sg * sr * be2;
+        R[5][ka] = -s * sg * sr * be1;
+    }
+    lam[3] = 0.0;
+    R[0][3] = 1.0;                                   /* entropy: density only */
+}
+
+/* Inverse of a 7 x 7 matrix by Gauss-Jordan elimination with partial
+ * pivoting (the left eigenvectors are the rows of the inverse of R). */
+static int invert7(double A[7][7], double X[7][7])
+{
+    double M[7][14];
+    for (int i = 0; i < 7; ++i)
+        for (int j = 0; j < 14; ++j) M[i][j] = j < 7 ? A[i][j] : (j - 7 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 7; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 7; ++i)
+            if (fabs(M[i][c]) > fabs(M[piv][c])) piv = i;
+        if (M[piv][c] == 0.0) return -1;
+        if (piv != c)
+            for (int j = 0; j < 14; ++j) { double t = M[c][j]; M[c][j] = M[piv][j]; M[piv][j] = t; }
+        double d = M[c][c];
+        for (int j = 0; j < 14; ++j) M[c][j] /= d;
+        for (int i = 0; i < 7; ++i) {
+            if (i == c || M[i][c] == 0.0) continue;
+            double f = M[i][c];
+            for (int j = 0; j < 14; ++j) M[i][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < 7; ++i)
+        for (int j = 0; j < 7; ++j) X[i][j] = M[i][j + 7];
+    return 0;
+}
+
+/* Interface states of one zone by full characteristic tracing (CW84's
+ * tracing with one reference state, for the seven Lagrangian MHD waves):
+ * at the right face the waves with positive speed arrive within dt, at the
+ * left face those with negative speed.  The reference state is the average
+ * of the zone's parabolas (aL, dA, a6 per primitive) over the domain of
+ * dependence of the fast wave, y = |lambda| dt / dm (at most 1); every
+ * slower wave that arrives is given the average over its own domain: the
+ * difference of the two averages is projected on that wave's left
+ * eigenvector and taken out along its right eigenvector.  WL: the state at
+ * the right face, WR: at the left face. */
+static void trace7(const double aL[7], const double dA[7], const double a6[7], const double lam[7],
+                   double R[7][7], double Li[7][7], double dt, double dm, double WL[7], double WR[7])
+{
+    for (int side = 0; side < 2; ++side) {
+        int kref = side == 0 ? 6 : 0;                 /* fast wave into this face */
+        int slower[2] = {side == 0 ? 5 : 1, side == 0 ? 4 : 2};
+        double *out = side == 0 ? WL : WR;
+        double yref = dmin(1.0, fabs(lam[kref]) * dt / dm);
+        double ref[7];
+        for (int v = 0; v < 7; ++v)
+            ref[v] = side == 0 ? par_avg_right_part(aL[v], dA[v], a6[v], yref)
+                               : par_avg_left_part(aL[v], dA[v], a6[v], yref);
+        for (int v = 0; v < 7; ++v) out[v] = ref[v];
+        for (int q = 0; q < 2; ++q) {
+            int k = slower[q];
+            if (lam[k] == 0.0) continue;              /* does not reach the face */
+            double y = dmin(1.0, fabs(lam[k]) * dt / dm);
+            double beta = 0.0;
+            for (int v = 0; v < 7; ++v) {
+                double avg = side == 0 ? par_avg_right_part(aL[v], dA[v], a6[v], y)
+                                       : par_avg_left_part(aL[v], dA[v], a6[v], y);
+                beta += Li[k][v] * (ref[v] - avg);
+            }
+            for (int v = 0; v < 7; ++v) out[v] -= beta * R[v][k];
+        }
+    }
+}
+
+/* The Riemann problem at a face in the mass coordinate, linearised about the
+ * mean of the two states: the face is at rest, so its state is the left
+ * state plus the jumps of the waves with negative speed, W* = W_L +
+ * sum_{lambda_k < 0} (l_k . (W_R - W_L)) r_k (the pairs of the two-family
+ * mode are solved separately; here all seven waves are one system).  W_L,
+ * W_R: primitives with B'_t; Bn: total normal field at the face; Bd1, Bd2:
+ * the background transverse field at the face. */
+static int riemann7(const double WL[7], const double WR[7], double g, double Bn, double Bd1, double Bd2,
+                    double Ws[7])
+{
+    double lam[7], R[7][7], Li[7][7];
+    mhd7_eigen(0.5 * (WL[0] + WR[0]), 0.5 * (WL[6] + WR[6]), g, Bn, Bd1 + 0.5 * (WL[4] + WR[4]),
+               Bd2 + 0.5 * (WL[5] + WR[5]), lam, R);
+    if (invert7(R, Li) != 0) return -1;
+    for (int v = 0; v < 7; ++v) Ws[v] = WL[v];
+    for (int k = 0; k < 7; ++k) {
+        if (!(lam[k] < 0.0)) continue;
+        double beta = 0.0;
+        for (int v = 0; v < 7; ++v) beta += Li[k][v] * (WR[v] - WL[v]);
+        for (int v = 0; v < 7; ++v) Ws[v] += beta * R[v][k];
+    }
+    return 0;
 }
 
 /* CW84 appendix shock detection / flattening coefficients on the transverse
@@ -388,6 +564,23 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
         double CA = sqrt(rho) * fabs(Bn);
         double yn = dmin(1.0, Cn * dt / dm[i]);
         double yA = dmin(1.0, CA * dt / dm[i]);
+        if (pr->tracing == 1) {
+            /* one traced state per face for both Riemann problems; the
+             * couplings between the pairs are in the eigenvectors */
+            double lam[7], R[7][7], Li[7][7], aL[7], dA[7], a6[7], WL[7], WR[7];
+            mhd7_eigen(rho, p, g, Bn, Bt1, Bt2, lam, R);
+            if (invert7(R, Li) != 0) abort();
+            for (int v = 0; v < 7; ++v) { aL[v] = pL[v][i]; dA[v] = pD[v][i]; a6[v] = p6[v][i]; }
+            trace7(aL, dA, a6, lam, R, Li, dt, dm[i], WL, WR);
+            Ln_rho[i] = LA_rho[i] = WL[W_RHO]; Rn_rho[i] = RA_rho[i] = WR[W_RHO];
+            Ln_u[i] = WL[W_U]; Rn_u[i] = WR[W_U];
+            Ln_p[i] = WL[W_P]; Rn_p[i] = WR[W_P];
+            Ln_b1[i] = LA_b1[i] = WL[W_B1]; Rn_b1[i] = RA_b1[i] = WR[W_B1];
+            Ln_b2[i] = LA_b2[i] = WL[W_B2]; Rn_b2[i] = RA_b2[i] = WR[W_B2];
+            LA_v1[i] = WL[W_V1]; RA_v1[i] = WR[W_V1];
+            LA_v2[i] = WL[W_V2]; RA_v2[i] = WR[W_V2];
+            corrP[i] = corrB1[i] = corrB2[i] = 0.0;
+        } else {
 #define TR(k, y, Ldst, Rdst) \
         Ldst[i] = par_avg_right_part(pL[k][i], pD[k][i], p6[k][i], y); \
         Rdst[i] = par_avg_left_part(pL[k][i], pD[k][i], p6[k][i], y);
@@ -408,6 +601,7 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
         corrP[i] = 0.5 * dt * rho * Bn * (Bt1 * pD[W_V1][i] + Bt2 * pD[W_V2][i]) / dm[i];
         corrB1[i] = -0.5 * dt * rho * Bt1 * pD[W_U][i] / dm[i];
         corrB2[i] = -0.5 * dt * rho * Bt2 * pD[W_U][i] / dm[i];
+        }
         /* terms from the variation of the normal field along the pencil
          * (zero in 1D, nonzero in a split multi-D step): mass-coordinate
          * derivatives of B'_n (centred) and of the dipole (face values) */
@@ -430,6 +624,32 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
     for (int i = 3; i <= M - 5; ++i) {   /* face i+1/2 between zones i, i+1 */
         double Bdn = Bdf[0][i], Bd1 = Bdf[1][i], Bd2 = Bdf[2][i];
         double Pd = 0.5 * (Bd1 * Bd1 + Bd2 * Bd2);
+        if (pr->tracing == 1) {
+            /* characteristic mode: the interface problem in its
+             * linearisation about the mean of the two traced states (with
+             * the time-centring terms of the split multi-D step) */
+            double WLs[7] = {Ln_rho[i], Ln_u[i] + corrU[i], LA_v1[i] + corrV1[i], LA_v2[i] + corrV2[i],
+                             Ln_b1[i] + corrB1[i], Ln_b2[i] + corrB2[i], Ln_p[i] + corrP[i]};
+            double WRs[7] = {Rn_rho[i + 1], Rn_u[i + 1] + corrU[i + 1], RA_v1[i + 1] + corrV1[i + 1],
+                             RA_v2[i + 1] + corrV2[i + 1], Rn_b1[i + 1] + corrB1[i + 1],
+                             Rn_b2[i + 1] + corrB2[i + 1], Rn_p[i + 1] + corrP[i + 1]};
+            double bns = 0.5 * (bn[i] + bn[i + 1]);
+            double Bns = Bdn + bns;
+            double Ws[7];
+            if (riemann7(WLs, WRs, g, Bns, Bd1, Bd2, Ws) != 0) abort();
+            double ust = Ws[1], v1s = Ws[2], v2s = Ws[3], b1s = Ws[4], b2s = Ws[5];
+            double Pst = Ws[6] + Bd1 * b1s + Bd2 * b2s + 0.5 * (b1s * b1s + b2s * b2s);
+            if (i >= NG - 1 && i <= NG + N - 1) st->iters_hist[0]++;   /* no iteration */
+            double nn = bns * (Bdn + 0.5 * bns);
+            F_pi[i] = Pst - nn;
+            F_v1[i] = -(Bns * b1s + bns * Bd1);
+            F_v2[i] = -(Bns * b2s + bns * Bd2);
+            F_b1[i] = ust * Bd1 - Bns * v1s;
+            F_b2[i] = ust * Bd2 - Bns * v2s;
+            F_e[i] = ust * (Pst + nn) - Bns * (ust * bns + v1s * b1s + v2s * b2s);
+            delta[i] = ust * dt;
+            continue;
+        }
         /* left state (zone i) */
         double rl = Ln_rho[i], ul = Ln_u[i] + corrU[i], pl = Ln_p[i], b1l = Ln_b1[i], b2l = Ln_b2[i];
         double T1l = Bd1 + b1l, T2l = Bd2 + b2l;
@@ -880,6 +1100,33 @@ void oracle_ppm_parabolas(int M, const double *a, const double *w, const double 
                      &out[j], &out[M + j], &out[2 * M + j]);
     free(slope);
     free(edge);
+}
+
+/* Test hooks of the full characteristic tracing: the eigen-structure at a
+ * state (lam[7], R row-major [7][7]) and the traced face states of one zone
+ * from its parabolas (a[7][3] = aL, dA, a6 per primitive). */
+void oracle_mhd7_eigen(double rho, double p, double g, double Bn, double Bt1, double Bt2, double *lam, double *Rflat)
+{
+    double R[7][7];
+    mhd7_eigen(rho, p, g, Bn, Bt1, Bt2, lam, R);
+    for (int i = 0; i < 7; ++i)
+        for (int k = 0; k < 7; ++k) Rflat[i * 7 + k] = R[i][k];
+}
+
+int oracle_riemann7(const double *WL, const double *WR, double g, double Bn, double Bd1, double Bd2, double *Ws)
+{
+    return riemann7(WL, WR, g, Bn, Bd1, Bd2, Ws);
+}
+
+int oracle_trace7(double rho, double p, double g, double Bn, double Bt1, double Bt2, const double *par, double dt,
+                  double dm, double *WL, double *WR)
+{
+    double lam[7], R[7][7], Li[7][7], aL[7], dA[7], a6[7];
+    mhd7_eigen(rho, p, g, Bn, Bt1, Bt2, lam, R);
+    if (invert7(R, Li) != 0) return -1;
+    for (int v = 0; v < 7; ++v) { aL[v] = par[v * 3]; dA[v] = par[v * 3 + 1]; a6[v] = par[v * 3 + 2]; }
+    trace7(aL, dA, a6, lam, R, Li, dt, dm, WL, WR);
+    return 0;
 }
 
 double oracle_par_avg(double aL, double dA, double a6, double y, int right_part)
