@@ -120,6 +120,8 @@ def lib():
         L.oracle_mhd7_eigen.restype = None
         L.oracle_trace7.argtypes = [C.c_double] * 6 + [dp, C.c_double, C.c_double, dp, dp]
         L.oracle_trace7.restype = C.c_int
+        L.oracle_face_states.argtypes = [C.POINTER(Problem), dp, C.c_double, C.c_int, C.c_int, C.c_int, dp]
+        L.oracle_face_states.restype = C.c_int
         L.oracle_riemann7.argtypes = [dp, dp] + [C.c_double] * 4 + [dp]
         L.oracle_riemann7.restype = C.c_int
         L.mlp_gelu.argtypes = [C.c_double]
@@ -199,6 +201,21 @@ class OracleProblem:
         if rc != 0:
             raise ValueError("oracle_sweep_pencils rejected its arguments")
         return out
+
+    def face_states(self, U: np.ndarray, dt: float, axis: int, j1: int, j2: int):
+        """Characteristic mode only: the two primitive states (rho, u, v_t1,
+        v_t2, B'_t1, B'_t2, p), after the split multi-D time-centring terms,
+        of the linearised interface problem at the faces of pencil (j1, j2)
+        of `axis`.  Returns (WL, WR), each [N + 1, 7], for the faces
+        -1/2 .. N - 1/2 of the pencil's zones."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        N = self.p.n[axis]
+        G = ghosts()
+        out = np.zeros((N + 2 * G, 14), dtype=np.float64)
+        if lib().oracle_face_states(C.byref(self.p), _dptr(U), dt, axis, j1, j2, _dptr(out)) != 0:
+            raise ValueError("oracle_face_states rejected its arguments")
+        f = out[G - 1:G + N]
+        return f[:, :7].copy(), f[:, 7:].copy()
 
     def step(self, U: np.ndarray, dt: float, step_index: int, stats: Stats | None = None) -> np.ndarray:
         U = np.ascontiguousarray(U, dtype=np.float64).copy()

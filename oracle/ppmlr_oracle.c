@@ -283,6 +283,18 @@ static void mhd7_eigen(double rho, double p, double g, double Bn, double Bt1, do
     R[0][3] = 1.0;                                   /* entropy: density only */
 }
 
+/* Waves of zero Lagrangian speed: where the normal field vanishes the Alfven
+ * and slow waves stop, and the traced face state jumps between the reference
+ * value (wave at rest) and the edge value (wave of speed 0+), with the
+ * Alfven family's eigenvector set by sgn(B_n).  A normal field that is zero
+ * in exact arithmetic (a background field cancelled by the deviation field)
+ * is rounding noise in any implementation, so the characteristic mode
+ * takes a wave slower than WAVE_MIN times the fast wave as at rest, in the
+ * tracing and in the interface problem: its domain of dependence is then
+ * below 1e-4 of the fast wave's, and the decision no longer rests on the
+ * sign of noise. */
+#define WAVE_MIN 1e-4
+
 /* Inverse of a 7 x 7 matrix by Gauss-Jordan elimination with partial
  * pivoting (the left eigenvectors are the rows of the inverse of R). */
 static int invert7(double A[7][7], double X[7][7])
@@ -335,7 +347,9 @@ static void trace7(const double aL[7], const double dA[7], const double a6[7], c
         for (int v = 0; v < 7; ++v) out[v] = ref[v];
         for (int q = 0; q < 2; ++q) {
             int k = slower[q];
-            if (lam[k] == 0.0) continue;              /* does not reach the face */
+            /* a wave slower than WAVE_MIN times the fast wave counts as not
+             * reaching the face (see WAVE_MIN) */
+            if (!(fabs(lam[k]) > WAVE_MIN * fabs(lam[kref]))) continue;
             double y = dmin(1.0, fabs(lam[k]) * dt / dm);
             double beta = 0.0;
             for (int v = 0; v < 7; ++v) {
@@ -364,7 +378,9 @@ static int riemann7(const double WL[7], const double WR[7], double g, double Bn,
     if (invert7(R, Li) != 0) return -1;
     for (int v = 0; v < 7; ++v) Ws[v] = WL[v];
     for (int k = 0; k < 7; ++k) {
-        if (!(lam[k] < 0.0)) continue;
+        /* waves of negative speed cross to the left; one slower than
+         * WAVE_MIN times the fast wave counts as at rest (see WAVE_MIN) */
+        if (!(lam[k] < -WAVE_MIN * fabs(lam[6]))) continue;
         double beta = 0.0;
         for (int v = 0; v < 7; ++v) beta += Li[k][v] * (WR[v] - WL[v]);
         for (int v = 0; v < 7; ++v) Ws[v] += beta * R[v][k];
@@ -471,7 +487,7 @@ typedef struct {
 static void sweep_pencil(const oracle_problem *pr, int axis, int N,
                          double *const U[NV], const double *dx, const double *xc,
                          const double *xf, double c1, double c2, double dt,
-                         double *const Uout[NV], oracle_stats *st)
+                         double *const Uout[NV], oracle_stats *st, double *face_states)
 {
     const int M = N + 2 * NG;
     const int n = axis, t1 = (axis + 1) % 3, t2 = (axis + 2) % 3;
@@ -572,6 +588,12 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
             if (invert7(R, Li) != 0) abort();
             for (int v = 0; v < 7; ++v) { aL[v] = pL[v][i]; dA[v] = pD[v][i]; a6[v] = p6[v][i]; }
             trace7(aL, dA, a6, lam, R, Li, dt, dm[i], WL, WR);
+            /* a traced state without positive density and pressure (no
+             * eigen-structure at the face) falls back to the zone average */
+            if (!(WL[W_RHO] > 0.0) || !(WL[W_P] > 0.0))
+                for (int v = 0; v < 7; ++v) WL[v] = W[v][i];
+            if (!(WR[W_RHO] > 0.0) || !(WR[W_P] > 0.0))
+                for (int v = 0; v < 7; ++v) WR[v] = W[v][i];
             Ln_rho[i] = LA_rho[i] = WL[W_RHO]; Rn_rho[i] = RA_rho[i] = WR[W_RHO];
             Ln_u[i] = WL[W_U]; Rn_u[i] = WR[W_U];
             Ln_p[i] = WL[W_P]; Rn_p[i] = WR[W_P];
@@ -626,16 +648,25 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
         double Pd = 0.5 * (Bd1 * Bd1 + Bd2 * Bd2);
         if (pr->tracing == 1) {
             /* characteristic mode: the interface problem in its
-             * linearisation about the mean of the two traced states (with
-             * the time-centring terms of the split multi-D step) */
+             * linearisation about the mean of the two traced states, with
+             * the time-centring terms of the split multi-D step on u, v_t
+             * and B_t.  The thermal pressure takes none: its Lagrangian
+             * equation has no term in the variation of B_n, and corrP is
+             * the magnetic-pressure change B_t . corrB that the corrected
+             * field already carries into the total pressure. */
             double WLs[7] = {Ln_rho[i], Ln_u[i] + corrU[i], LA_v1[i] + corrV1[i], LA_v2[i] + corrV2[i],
-                             Ln_b1[i] + corrB1[i], Ln_b2[i] + corrB2[i], Ln_p[i] + corrP[i]};
+                             Ln_b1[i] + corrB1[i], Ln_b2[i] + corrB2[i], Ln_p[i]};
             double WRs[7] = {Rn_rho[i + 1], Rn_u[i + 1] + corrU[i + 1], RA_v1[i + 1] + corrV1[i + 1],
                              RA_v2[i + 1] + corrV2[i + 1], Rn_b1[i + 1] + corrB1[i + 1],
-                             Rn_b2[i + 1] + corrB2[i + 1], Rn_p[i + 1] + corrP[i + 1]};
+                             Rn_b2[i + 1] + corrB2[i + 1], Rn_p[i + 1]};
             double bns = 0.5 * (bn[i] + bn[i + 1]);
             double Bns = Bdn + bns;
             double Ws[7];
+            if (face_states)    /* test hook: the two states of the solve */
+                for (int v = 0; v < 7; ++v) {
+                    face_states[i * 14 + v] = WLs[v];
+                    face_states[i * 14 + 7 + v] = WRs[v];
+                }
             if (riemann7(WLs, WRs, g, Bns, Bd1, Bd2, Ws) != 0) abort();
             double ust = Ws[1], v1s = Ws[2], v2s = Ws[3], b1s = Ws[4], b2s = Ws[5];
             double Pst = Ws[6] + Bd1 * b1s + Bd2 * b2s + 0.5 * (b1s * b1s + b2s * b2s);
@@ -915,7 +946,7 @@ int oracle_sweep(const oracle_problem *pr, double *U3, double dt, int axis, orac
         for (int pidx = 0; pidx < npen; ++pidx) {
             int j1 = pidx % pr->n[t1], j2 = pidx / pr->n[t1];
             extract_pencil(pr, src, a, j1, j2, xc, xc1[j1], xc2[j2], P);
-            sweep_pencil(pr, a, N, P, dx, xc, xf, xc1[j1], xc2[j2], dt, O, &loc);
+            sweep_pencil(pr, a, N, P, dx, xc, xf, xc1[j1], xc2[j2], dt, O, &loc, NULL);
             for (int s = 0; s < N; ++s) {
                 int ijk[3];
                 pencil_ijk(a, s, j1, j2, ijk);
@@ -976,7 +1007,7 @@ int oracle_sweep_pencils(const oracle_problem *pr, const double *U3, double dt, 
             double c2 = 0.5 * (pr->faces[t2][j2] + pr->faces[t2][j2 + 1]);
             for (int v = 0; v < NV; ++v) O[v] = out + ((size_t)p * NV + v) * N;
             extract_pencil(pr, U3, a, j1, j2, xc, c1, c2, P);
-            sweep_pencil(pr, a, N, P, dx, xc, xf, c1, c2, dt, O, &loc);
+            sweep_pencil(pr, a, N, P, dx, xc, xf, c1, c2, dt, O, &loc, NULL);
         }
 #pragma omp critical
         {
@@ -995,6 +1026,35 @@ int oracle_sweep_pencils(const oracle_problem *pr, const double *U3, double dt, 
     }
     free(dx); free(xc); free(xf);
     return bad ? -1 : 0;
+}
+
+/* Test hook (characteristic mode): sweep one pencil (j1, j2) of `axis` and
+ * write the two primitive states (W_L, W_R, 7 values each, after the split
+ * multi-D time-centring terms) of the linearised interface problem at every
+ * face: out[14 * i ...] for the face between pencil zones i - NG and
+ * i - NG + 1, i = 3 .. N + NG + 2; out holds 14 (N + 2 NG) values. */
+int oracle_face_states(const oracle_problem *pr, const double *U3, double dt, int axis, int j1, int j2,
+                       double *out)
+{
+    if (check_problem(pr, axis) != 0 || !(dt > 0.0) || pr->tracing != 1) return -1;
+    const int a = axis, t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+    if (j1 < 0 || j1 >= pr->n[t1] || j2 < 0 || j2 >= pr->n[t2]) return -1;
+    const int N = pr->n[a], M = N + 2 * NG;
+    double *dx = malloc(sizeof(double) * (M + 1)), *xc = malloc(sizeof(double) * (M + 1));
+    double *xf = malloc(sizeof(double) * (M + 2));
+    double *pbuf = malloc(sizeof(double) * NV * (M + 1)), *obuf = malloc(sizeof(double) * NV * N);
+    double *P[NV], *O[NV];
+    for (int v = 0; v < NV; ++v) { P[v] = pbuf + v * (M + 1); O[v] = obuf + v * N; }
+    axis_geometry(pr, a, dx, xc, xf);
+    for (int i = 0; i < 14 * M; ++i) out[i] = 0.0;
+    double c1 = 0.5 * (pr->faces[t1][j1] + pr->faces[t1][j1 + 1]);
+    double c2 = 0.5 * (pr->faces[t2][j2] + pr->faces[t2][j2 + 1]);
+    oracle_stats loc;
+    memset(&loc, 0, sizeof(loc));
+    extract_pencil(pr, U3, a, j1, j2, xc, c1, c2, P);
+    sweep_pencil(pr, a, N, P, dx, xc, xf, c1, c2, dt, O, &loc, out);
+    free(dx); free(xc); free(xf); free(pbuf); free(obuf);
+    return 0;
 }
 
 /* One split step: x, y, z sweeps on even steps, z, y, x on odd steps, all

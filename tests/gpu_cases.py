@@ -32,6 +32,7 @@ class Case:
     p_floor: float = 1e-8
     tol64: float = 1e-12
     tol32: float = 1e-6
+    tracing: int = 0                    # 0: two-family tracing, 1: characteristic mode
     meta: dict = field(default_factory=dict)
 
     def oracle(self, tol=None):
@@ -40,12 +41,13 @@ class Case:
                                dip_dir=self.dip_dir, bext=self.bext, inflow=self.inflow,
                                r_inner=self.r_inner, inner_rho=self.inner_rho, inner_p=self.inner_p,
                                flatten=self.flatten, janhunen=self.janhunen, max_iter=self.max_iter,
-                               tol=self.tol64 if tol is None else tol, p_floor=self.p_floor)
+                               tol=self.tol64 if tol is None else tol, p_floor=self.p_floor,
+                               tracing=self.tracing)
 
     def context(self, **over):
         from paper_1607_02214_amd import ppmlr
         opt = dict(flatten=int(self.flatten), janhunen=int(self.janhunen), max_iter=self.max_iter,
-                   tol_f64=self.tol64, tol_f32=self.tol32, p_floor=self.p_floor)
+                   tol_f64=self.tol64, tol_f32=self.tol32, p_floor=self.p_floor, tracing=self.tracing)
         opt.update(over)
         ctx = ppmlr.Context(self.faces, self.bc_lo, self.bc_hi, r_inner=self.r_inner, **opt)
         if self.dip_moment != 0.0:
@@ -104,14 +106,37 @@ def normwise_errors(gpu: np.ndarray, ref: np.ndarray):
     return np.max(np.abs(g - r), axis=1) / scale
 
 
-def pointwise_errors(gpu: np.ndarray, ref: np.ndarray, floor: float = 1e-6):
+FAMILIES = ((0,), (1, 2, 3), (4, 5, 6), (7,))
+
+
+def familywise_errors(gpu: np.ndarray, ref: np.ndarray):
+    """Per conserved variable: max |gpu - ref| over the largest |ref| of its
+    family (mass; the three momentum components; the three field components;
+    energy), so that a component that vanishes in exact arithmetic (the
+    transverse momentum of a blast at rest) is measured against its
+    family's scale instead of its own rounding noise."""
+    g = gpu.reshape(8, -1).astype(np.float64)
+    r = ref.reshape(8, -1).astype(np.float64)
+    out = np.zeros(8)
+    for fam in FAMILIES:
+        scale = max(float(np.max(np.abs(r[list(fam)]))), 1e-300)
+        for q in fam:
+            out[q] = float(np.max(np.abs(g[q] - r[q]))) / scale
+    return out
+
+
+def pointwise_errors(gpu: np.ndarray, ref: np.ndarray, floor: float = 1e-6, by_family: bool = False):
     """Per conserved variable: max_i |gpu_i - ref_i| / max(|ref_i|, floor *
     max |ref|), the pointwise form of the error metric (each zone against its
     own magnitude, so that a small-valued region is not measured against the
-    largest value elsewhere in the box)."""
+    largest value elsewhere in the box).  by_family: the floor is taken from
+    the largest |ref| of the variable's family (see familywise_errors)."""
     g = gpu.reshape(8, -1).astype(np.float64)
     r = ref.reshape(8, -1).astype(np.float64)
     scale = np.maximum(np.max(np.abs(r), axis=1), 1e-300)
+    if by_family:
+        for fam in FAMILIES:
+            scale[list(fam)] = max(float(np.max(scale[list(fam)])), 1e-300)
     den = np.maximum(np.abs(r), floor * scale[:, None])
     return np.max(np.abs(g - r) / den, axis=1)
 

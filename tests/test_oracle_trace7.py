@@ -16,7 +16,19 @@ against what the mathematics fixes:
   axis and oblique, beside the two-family mode's error on the same runs;
 - the Sod shock tube (B = 0) converging to the exact solution;
 - uniform states kept bitwise and mass, momentum and energy conserved on a
-  periodic box."""
+  periodic box;
+- the split multi-D terms (B_n varying along the pencil) on a pencil whose
+  primitive variables are uniform: the thermal pressure and density of both
+  face states stay exactly the zone values (the Lagrangian equations of rho
+  and p have no term in dB_n/dm), while the transverse field and velocity
+  take the time-centring terms, so the magnetic-pressure change reaches the
+  total pressure through the field alone;
+- the inflow/dipole set-up (strong background field near the inner
+  boundary) kept finite with positive density and pressure;
+- a normal field at rounding level (a background field cancelled by the
+  deviation field) decides nothing: the traced states and the interface
+  state at B_n = 0 and at B_n = +-1e-14 agree, while a normal field well
+  above the noise moves them."""
 import numpy as np
 import pytest
 
@@ -196,3 +208,70 @@ def test_uniform_state_bitwise_and_periodic_conservation():
     t0, t1 = prob.totals(Uc), prob.totals(U1)
     for q in (0, 1, 2, 3, 7):
         assert abs(t1[q] - t0[q]) <= 1e-13 * max(abs(t0[q]), 1.0), (q, t0[q], t1[q])
+
+
+def test_split_multid_terms_leave_rho_and_p_and_move_the_field():
+    N = 24
+    faces = [I.uniform_faces(N), I.uniform_faces(1), I.uniform_faces(1)]
+    xc = I.centres(faces[0])
+    rho, p = 1.3, 0.9
+    vt, bt = (0.4, -0.3), (0.7, 0.5)
+    # B'_x varies along the pencil (as it does in a split multi-D step)
+    bx = 0.8 + 0.2 * np.sin(2 * np.pi * xc)
+    one = np.ones(N)
+    U = I.conserved(rho * one, 0 * one, vt[0] * one, vt[1] * one, bx, bt[0] * one, bt[1] * one, p * one,
+                    G)[:, None, None, :]
+    prob = O.OracleProblem(faces, tracing=1)
+    dt = prob.cfl_dt(U, 0.4)
+    WL, WR = prob.face_states(U, dt, 0, 0, 0)
+    for W in (WL, WR):
+        # (the zone values themselves are recovered from the conserved
+        # energy, so they sit within a few ulps of p)
+        assert np.max(np.abs(W[:, 0] - rho)) <= 1e-14, W[:, 0] - rho
+        assert np.max(np.abs(W[:, 6] - p)) <= 1e-14, W[:, 6] - p
+        assert np.all(W[:, 1] != 0.0)                 # u takes B_n dB_n/dm
+        # the field moves with the time-centring terms (rho v_t dB_n/dm)
+        assert np.max(np.abs(W[:, 4] - bt[0])) > 1e-3
+        assert np.max(np.abs(W[:, 5] - bt[1])) > 1e-3
+    with pytest.raises(ValueError):
+        O.OracleProblem(faces, tracing=0).face_states(U, dt, 0, 0, 0)
+
+
+def test_inflow_dipole_stays_finite_and_positive():
+    import gpu_cases as GC
+    case = GC.dipole_case()
+    case.tracing = 1
+    prob = case.oracle()
+    U = case.U.copy()
+    for s in range(3):
+        U = prob.step(U, prob.cfl_dt(U, 0.4), s)
+    assert np.all(np.isfinite(U))
+    rho = U[0]
+    p = (G - 1) * (U[7] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / rho - 0.5 * (U[4] ** 2 + U[5] ** 2 + U[6] ** 2))
+    assert rho.min() > 0 and p.min() > 0
+
+
+def test_rounding_level_normal_field_decides_nothing():
+    rng = np.random.default_rng(11)
+    rho, p, Bt1, Bt2 = 1.2, 0.9, 0.7, -0.4
+    # parabolas with gradients in every primitive (v_t and B_t included)
+    base = np.array([rho, 0.1, 0.3, -0.2, 0.0, 0.0, p])
+    par = np.zeros((7, 3))
+    par[:, 0] = base + 0.05 * rng.standard_normal(7)      # left edge
+    par[:, 1] = 0.1 * rng.standard_normal(7)              # aR - aL
+    par[:, 2] = 0.02 * rng.standard_normal(7)             # a6
+    dt, dm = 0.05, 1.0
+    tr0 = O.trace7(rho, p, G, 0.0, Bt1, Bt2, par, dt, dm)
+    WL0, WR0 = tr0
+    WRn = WR0 + 0.03 * rng.standard_normal(7)
+    rs0 = O.riemann7(WL0, WRn, G, 0.0, 0.2, -0.1)
+    for Bn in (1e-14, -1e-14):
+        WL, WR = O.trace7(rho, p, G, Bn, Bt1, Bt2, par, dt, dm)
+        assert np.max(np.abs(WL - WL0)) <= 1e-12 and np.max(np.abs(WR - WR0)) <= 1e-12, (Bn, WL - WL0, WR - WR0)
+        rs = O.riemann7(WL0, WRn, G, Bn, 0.2, -0.1)
+        assert np.max(np.abs(rs - rs0)) <= 1e-12, (Bn, rs - rs0)
+    # a normal field well above the noise: the Alfven and slow waves take part
+    WL, WR = O.trace7(rho, p, G, 0.05, Bt1, Bt2, par, dt, dm)
+    assert np.max(np.abs(WL - WL0)) > 1e-4
+    rs = O.riemann7(WL0, WRn, G, 0.05, 0.2, -0.1)
+    assert np.max(np.abs(rs - rs0)) > 1e-4
