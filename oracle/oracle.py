@@ -110,7 +110,7 @@ def lib():
         L.oracle_ppm_parabolas.argtypes = [C.c_int, dp, dp, dp, C.c_int, C.c_int, dp]
         L.oracle_par_avg.argtypes = [C.c_double] * 4 + [C.c_int]
         L.oracle_par_avg.restype = C.c_double
-        L.oracle_flattening.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.oracle_flattening.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         L.oracle_riemann_normal.argtypes = [C.c_double] * 9 + [C.c_double, C.c_int, dp, dp, ip]
         L.oracle_riemann_normal.restype = C.c_int
         L.oracle_riemann_alfven.argtypes = [C.c_double] * 7 + [dp, dp]
@@ -318,12 +318,15 @@ def par_avg(aL, dA, a6, y, right_part):
     return lib().oracle_par_avg(aL, dA, a6, y, int(right_part))
 
 
-def flattening(Pt, Pa, un):
+def flattening(Pt, Pa, un, rho=None):
+    """CW84 flattening coefficients of a pencil (rho: density, ones if not
+    given; it sets the speed scale of the compression test's margin)."""
     Pt = np.ascontiguousarray(Pt, dtype=np.float64)
     Pa = np.ascontiguousarray(Pa, dtype=np.float64)
     un = np.ascontiguousarray(un, dtype=np.float64)
+    rho = np.ones_like(Pt) if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
     f = np.zeros_like(Pt)
-    lib().oracle_flattening(len(Pt), _dptr(Pt), _dptr(Pa), _dptr(un), _dptr(f))
+    lib().oracle_flattening(len(Pt), _dptr(Pt), _dptr(Pa), _dptr(un), _dptr(rho), _dptr(f))
     return f
 
 

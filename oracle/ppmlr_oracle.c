@@ -391,8 +391,15 @@ static int riemann7(const double WL[7], const double WR[7], double g, double Bn,
 /* CW84 appendix shock detection / flattening coefficients on the transverse
  * total pressure.  Pt: perturbation pressure differences are taken on it;
  * Pa: absolute (positive) pressure for the relative-jump test; un: normal
- * velocity.  Constants eps = 0.33, omega1 = 0.75, omega2 = 10. */
-static void flattening(int M, const double *Pt, const double *Pa, const double *un,
+ * velocity; rho: density.  Constants eps = 0.33, omega1 = 0.75, omega2 = 10.
+ * The compression test u_{j-1} > u_{j+1} is taken with a margin of COMP_MIN
+ * times the speed sqrt(P_min / rho_j) of the jump test's pressure: at a
+ * pressure jump at rest the two velocities are equal, and a strict
+ * comparison would let rounding noise (which two implementations produce
+ * differently) switch full flattening on or off; no shock compresses at
+ * 1e-5 of a sound speed. */
+#define COMP_MIN 1e-5
+static void flattening(int M, const double *Pt, const double *Pa, const double *un, const double *rho,
                        double *ftil, double *f)
 {
     const double eps = 0.33, om1 = 0.75, om2 = 10.0;
@@ -400,8 +407,9 @@ static void flattening(int M, const double *Pt, const double *Pa, const double *
     for (int j = 2; j <= M - 3; ++j) {
         double d1 = Pt[j + 1] - Pt[j - 1];
         double d2 = Pt[j + 2] - Pt[j - 2];
+        double pmin = dmin(Pa[j + 1], Pa[j - 1]);
         double ft = 0.0;
-        if (fabs(d1) > eps * dmin(Pa[j + 1], Pa[j - 1]) && un[j - 1] > un[j + 1]) {
+        if (fabs(d1) > eps * pmin && un[j - 1] - un[j + 1] > COMP_MIN * sqrt(pmin / rho[j])) {
             if (d2 != 0.0) ft = dmax(0.0, dmin(1.0, om2 * (d1 / d2 - om1)));
             else ft = 1.0;
         }
@@ -563,7 +571,7 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
     }
 
     /* ---- step a3: parabolas in the mass coordinate ---- */
-    if (pr->flatten) flattening(M, Pt, Pa, W[W_U], ftil, fl);
+    if (pr->flatten) flattening(M, Pt, Pa, W[W_U], W[W_RHO], ftil, fl);
     else for (int i = 0; i < M; ++i) fl[i] = 0.0;
     for (int k = 0; k < NW; ++k) {
         ppm_edges(M, W[k], dm, 1, slope, edge);
@@ -1194,10 +1202,10 @@ double oracle_par_avg(double aL, double dA, double a6, double y, int right_part)
     return right_part ? par_avg_right_part(aL, dA, a6, y) : par_avg_left_part(aL, dA, a6, y);
 }
 
-void oracle_flattening(int M, const double *Pt, const double *Pa, const double *un, double *f)
+void oracle_flattening(int M, const double *Pt, const double *Pa, const double *un, const double *rho, double *f)
 {
     double *ft = malloc(sizeof(double) * M);
-    flattening(M, Pt, Pa, un, ft, f);
+    flattening(M, Pt, Pa, un, rho, ft, f);
     free(ft);
 }
 

@@ -149,6 +149,22 @@ def test_flattening_off_for_smooth_data_and_on_at_a_sharp_shock():
     assert np.all(f == 0.0)
 
 
+def test_flattening_compression_margin_at_a_jump_at_rest():
+    # a strong pressure jump at rest: equal velocities, or velocities that
+    # differ by rounding noise, never flatten; a compression well above the
+    # margin (1e-5 of sqrt(P/rho)) does
+    M = 40
+    x = np.arange(M)
+    Pt = np.where(x < 20, 20.0, 1.0)
+    rho = np.where(x < 20, 2.0, 1.0)
+    # (velocities falling along the pencil: a compression at noise level)
+    for un in (np.zeros(M), 1e-18 * (M - x), 1e-9 * (M - x) / M):
+        assert np.all(O.flattening(Pt, Pt, un, rho) == 0.0)
+    un = np.where(x < 20, 1e-3, 0.0)
+    f = O.flattening(Pt, Pt, un, rho)
+    assert f[19] > 0.0 and f[20] > 0.0
+
+
 def test_parabolas_with_full_flattening_are_constant():
     rng = np.random.default_rng(5)
     w, _ = _grid(rng, 20)

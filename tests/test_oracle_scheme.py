@@ -1,7 +1,8 @@
 """Pins of the full oracle sweep / split step against what the mathematics
 fixes: exact preservation of uniform and static-dipole states, conservation
-on periodic boxes, symmetries, linear MHD eigenmode convergence, and the
-exact gas-dynamic solution in the B = 0 limit.
+on periodic boxes, symmetries, linear MHD eigenmode convergence, the
+exact gas-dynamic solution in the B = 0 limit, and continuity of a sweep
+under rounding noise where the method has a tie (a pressure jump at rest).
 
 Paper: Section II (conservative ideal MHD with B = B_d + B', zone-centred
 averages, parabolic reconstruction, Lagrangian update + remap) and the
@@ -251,3 +252,26 @@ def test_rejects_bad_arguments():
     bad[3] = bad[2]
     with pytest.raises(ValueError):
         O.OracleProblem([bad, f, f]).sweep(U, 1e-3, 0)
+
+
+@pytest.mark.parametrize("tracing", [0, 1])
+def test_sweep_of_a_jump_at_rest_is_continuous_in_rounding_noise(tracing):
+    # a blast at rest after its x sweep: the y and z velocities are zero (or
+    # rounding noise, in the characteristic mode) across the strong pressure
+    # jump; noise of 1e-18 in them must not move the next sweep (it switched
+    # full flattening on at the front when the compression test was strict)
+    import gpu_cases as GC
+    case = GC.blast_case()
+    case.tracing = tracing
+    prob = case.oracle()
+    dt = prob.cfl_dt(case.U, 0.4)
+    U1 = prob.sweep(case.U, dt, 0)
+    rng = np.random.default_rng(0)
+    V = U1.copy()
+    V[2] += 1e-18 * rng.standard_normal(V[2].shape)
+    V[3] += 1e-18 * rng.standard_normal(V[3].shape)
+    for axis in (1, 2):
+        a = prob.sweep(U1, dt, axis)
+        b = prob.sweep(V, dt, axis)
+        err = GC.familywise_errors(b, a)
+        assert np.all(err <= 1e-12), (axis, err)
