@@ -27,16 +27,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (packed); 78.6 without packed FP32 instructions
-FP32_UNPACKED_TFLOPS = 78.6
-# FP32 operations per zone-sweep: adds + multiplies + transcendentals + 2 x
-# fused multiply-adds per lane, from the SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F32
-# counters of the sweep kernels on this workload (x 1203, y 1124, z 1138;
-# the smallest is used; ghost zones of pencil segments are not counted; the
-# Newton loop runs to each wave's slowest lane, so the figure moves by ~1 %
-# with the tile shape).  The committed counter summary's own figure is used
-# when it was taken from the current kernel source.
-FLOPS_PER_ZONE_SWEEP = 1124.0
+FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 with packed FP32 instructions (not generated here)
+FP32_UNPACKED_TFLOPS = 78.6       # the same without packed instructions: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz
+# Floating-point operations of one zone-sweep of the method (additions and
+# subtractions, multiplications, divisions, square roots), counted by the
+# oracle's instrumented build (oracle/flop_count.py: 64 random pencils per
+# axis of this workload's start state, FP32 Newton tolerance; the plain
+# oracle recomputes the width weights that the kernels share between the 7
+# reconstructed variables, so this is above what the kernels execute).
+FLOPS_PER_ZONE_SWEEP = 1875.8
+FLOPS_SOURCE = "oracle instrumented count (oracle/flop_count.py, 64 pencils per axis of the start state)"
+# What the kernels execute: FP32 operations per lane (ADD + MUL + TRANS + 2 FMA)
+# of the y sweep from its VALU counters (committed counter summary).
+KERNEL_FP32_OPS_PER_LANE = 1124.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -167,11 +170,17 @@ def series_leg(args, setup, make_ctx, shape_ctx):
             "finite": bool(torch.isfinite(u).all().item())}
 
 
-def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
+def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain, ref64=None):
     """The learned Riemann guess on the same workload: harvest interface
     records from a plain FP32 run of the start state, train the network on
     them with the GPU kernels, then time the learned-guess run over the same
-    warm-up + timed steps as the plain run and compare the final states."""
+    warm-up + timed steps as the plain run and compare the final states (with
+    the FP32 plain run, and with the FP64 reference run ref64 = (ctx, state)
+    of the same step count when given).  Cost breakdown, all three on the
+    learned run's tile shapes over the same steps: plain guess; the learned
+    mode with a network whose outputs are not finite, so that every selected
+    face runs the network and then falls back to the plain guess (the
+    network pass at the plain iteration count); the trained network."""
     import numpy as np
     import torch
     from paper_1607_02214_amd import learned, ppmlr
@@ -223,7 +232,51 @@ def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
 
     a, b = prim(u), prim(u_plain)
     err = {k: float((a[k] - b[k]).abs().max() / b[k].abs().max()) for k in a}
-    return {
+
+    def same_tiles(c):
+        # segments first: the tile width is checked against the segment length
+        for ax in range(3):
+            c.set_segments(ax, ctx.get_segments(ax))
+            c.set_segment_order(ax, ctx.get_segment_order(ax))
+            c.set_tile(ax, ctx.get_tile(ax, ppmlr.F32))
+
+    def timed(c):
+        w = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
+        c.advance(w, args.warmup, args.cfl)
+        torch.cuda.synchronize()
+        c.reset_stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.advance(w, args.steps, args.cfl)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps, iters(c.stats())
+
+    c_plain = make_ctx()
+    same_tiles(c_plain)
+    ms_plain, it_plain = timed(c_plain)
+    th_nan = theta.clone()
+    th_nan[-2:] = float("nan")                 # output biases: every network output non-finite
+    c_fb = make_ctx()
+    c_fb.set_guess(ppmlr.GUESS_LEARNED, th_nan)
+    same_tiles(c_fb)
+    ms_fb, it_fb = timed(c_fb)
+    fb_stats = c_fb.stats()
+    c_tr = make_ctx()
+    c_tr.set_guess(ppmlr.GUESS_LEARNED, theta)
+    same_tiles(c_tr)
+    ms_tr, it_tr = timed(c_tr)
+    breakdown = {
+        "tiles": tiles,
+        "ms_per_step": {"plain": round(ms_plain, 4), "network_all_fallback": round(ms_fb, 4),
+                        "trained": round(ms_tr, 4)},
+        "newton_iterations": {"plain": it_plain, "network_all_fallback": it_fb, "trained": it_tr},
+        "network_pass_ms_per_step": round(ms_fb - ms_plain, 4),
+        "iterations_saved_ms_per_step": round(ms_fb - ms_tr, 4),
+        "all_fallback_faces": {"selected": fb_stats["guess_faces"], "fallbacks": fb_stats["guess_fallbacks"]},
+    }
+    del c_plain, c_fb, c_tr
+    out = {
         "value": value,
         "unit": "zone-updates/s",
         "ms_per_step": ms / args.steps,
@@ -238,7 +291,12 @@ def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain):
                     "records_kept": min(offered, args.harvest_cap), "seconds": round(t_h, 2)},
         "training": {"adam_steps": args.train_steps, "batch": 4096, "lr": 1e-3, "seconds": round(t_t, 2),
                      "loss_first": hist[0][1], "loss_last": hist[-1][1]},
+        "cost_breakdown": breakdown,
     }
+    if ref64 is not None:
+        out["fp32_vs_fp64"] = fp32_vs_fp64(ctx, u, ref64[0], ref64[1])
+        out["fp32_vs_fp64"]["after_steps"] = args.warmup + args.steps
+    return out
 
 
 def ensemble_leg(args):
@@ -250,21 +308,47 @@ def ensemble_leg(args):
     from paper_1607_02214_amd import ppmlr
 
     spec = I.ensemble_members(count=32, seed=4)
-    ctxs, us, zones = [], [], 0
+    setups = []
     for m in spec:
         faces = I.member_faces(m["N"])
         sw = m["sw"]
-        st = I.DipoleSetup(faces=faces, U=I.dipole_initial_state(faces, sw), inflow=sw, inner_rho=sw[0],
-                           inner_p=sw[7], p_floor=1e-8 * sw[7])
+        setups.append(I.DipoleSetup(faces=faces, U=I.dipole_initial_state(faces, sw), inflow=sw, inner_rho=sw[0],
+                                    inner_p=sw[7], p_floor=1e-8 * sw[7]))
+
+    def member_ctx(st):
         c = ppmlr.Context(st.faces, st.bc_lo, st.bc_hi, r_inner=st.r_inner, p_floor=st.p_floor)
         c.set_dipole(st.moment, st.direction)
         c.set_inflow(st.inflow)
         c.set_inner(st.inner_rho, st.inner_p)
-        ctxs.append(c)
-        us.append(torch.from_numpy(st.U).to("cuda", torch.float32).contiguous())
-        zones += m["N"] ** 3
+        return c
+
+    ctxs = [member_ctx(st) for st in setups]
+    us = [torch.from_numpy(st.U).to("cuda", torch.float32).contiguous() for st in setups]
+    zones = sum(m["N"] ** 3 for m in spec)
     print(f"[bench] ensemble: {len(spec)} members, {zones} zones", file=sys.stderr, flush=True)
+    ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PER_SWEEP)
     block = ppmlr.ensemble_autotune(ctxs, us, reps=1)
+    # the same 10 steps in each launch form, on copies of the states with
+    # contexts of their own (the autotuned segments)
+    forms = {}
+    for name, mode in (("persistent", ppmlr.ENSEMBLE_PERSISTENT), ("per_sweep", ppmlr.ENSEMBLE_PER_SWEEP)):
+        ppmlr.set_ensemble_launch(mode)
+        cx = [member_ctx(st) for st in setups]
+        for c, c0 in zip(cx, ctxs):
+            for a in range(3):
+                c.set_segments(a, c0.get_segments(a))
+        ws = [u.clone() for u in us]
+        ppmlr.ensemble_run(cx, ws, 1, args.cfl)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ppmlr.ensemble_run(cx, ws, 10, args.cfl)
+        e1.record()
+        torch.cuda.synchronize()
+        forms[name] = {"ms_per_step": e0.elapsed_time(e1) / 10,
+                       "value": zones * 10 / (e0.elapsed_time(e1) / 1000.0)}
+        del ws, cx
+    ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PER_SWEEP)
     ppmlr.ensemble_run(ctxs, us, 2, args.cfl)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -283,13 +367,92 @@ def ensemble_leg(args):
         "zones": zones,
         "steps": args.ensemble_steps,
         "ms_per_step": ms / args.ensemble_steps,
+        "launch": "per sweep (one launch per sweep over every member, a dt kernel per step)",
         "block": block,
+        "launch_forms_10_steps": forms,
         "segments_of_largest_member": [ctxs[max(range(len(spec)), key=lambda k: spec[k]["N"])].get_segments(a)
                                        for a in range(3)],
         "status": sorted(set(status)),
         "finite": finite,
         "simulated_time_range": [min(times), max(times)],
     }
+
+
+def fp32_vs_fp64(ctx32, u32, ctx64, u64, gamma=5.0 / 3.0):
+    """Error of an FP32 run against the FP64 run of the same workload and
+    step count: per field (rho, p, |B'|) the normwise max |f32 - f64| /
+    max |f64| and the pointwise max |f32 - f64| / max(|f64|, 1e-6 max |f64|);
+    the drift of the FP64 domain totals (rho, |m|, |B'|, E) between the runs,
+    |sum32 - sum64| / |sum64|; and the simulated times of both runs."""
+    import numpy as np
+    import torch
+
+    def prim(U):
+        U = U.double()
+        rho = U[0]
+        v2 = (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / (rho * rho)
+        b2 = U[4] ** 2 + U[5] ** 2 + U[6] ** 2
+        return {"rho": rho, "p": (gamma - 1.0) * (U[7] - 0.5 * rho * v2 - 0.5 * b2), "|B'|": torch.sqrt(b2)}
+
+    a, b = prim(u32), prim(u64)
+    normwise, pointwise = {}, {}
+    for k in a:
+        d = (a[k] - b[k]).abs()
+        scale = b[k].abs().max()
+        normwise[k] = float(d.max() / scale)
+        pointwise[k] = float((d / torch.clamp(b[k].abs(), min=1e-6 * float(scale))).max())
+        del d
+    del a, b
+    t32 = np.array(ctx32.totals(u32))
+    t64 = np.array(ctx64.totals(u64))
+    drift = {"rho": abs(t32[0] - t64[0]) / abs(t64[0]),
+             "|m|": float(np.linalg.norm(t32[1:4] - t64[1:4]) / np.linalg.norm(t64[1:4])),
+             "|B'|": float(np.linalg.norm(t32[4:7] - t64[4:7]) / np.linalg.norm(t64[4:7])),
+             "E": abs(t32[7] - t64[7]) / abs(t64[7])}
+    return {"normwise": normwise, "pointwise": pointwise, "totals_drift": drift,
+            "simulated_time": {"f32": ctx32.time(u32), "f64": ctx64.time(u64)}}
+
+
+def c3_leg(args, make_ctx_for):
+    """The 512 x 384 x 384 form of the workload (every cell of the bench grid
+    split in two, 75.5 M zones): the FP32 run (tile search after 2 warm-up
+    steps, then args.c3_steps timed steps, FP64 dt and totals) and its error
+    against an FP64 run of the same steps from the same start."""
+    import numpy as np
+    import torch
+    from paper_1607_02214_amd import inputs as I
+
+    t0 = time.perf_counter()
+    setup = I.c3_setup(dtype=np.float64)
+    n = [len(f) - 1 for f in setup.faces]
+    zones = int(np.prod(n))
+    print(f"[bench] c3: grid {n[0]}x{n[1]}x{n[2]} built in {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+          flush=True)
+    warm = 2
+    ctx = make_ctx_for(setup)
+    u = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
+    ctx.advance(u, warm, args.cfl)
+    torch.cuda.synchronize()
+    ctx.autotune(u, reps=3)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ctx.advance(u, args.c3_steps, args.cfl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ctx64 = make_ctx_for(setup)
+    u64 = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float64).contiguous()
+    del setup
+    ctx64.advance(u64, warm + args.c3_steps, args.cfl)
+    torch.cuda.synchronize()
+    err = fp32_vs_fp64(ctx, u, ctx64, u64)
+    out = {"value": zones * args.c3_steps / (ms / 1000.0), "unit": "zone-updates/s", "grid": n,
+           "steps": args.c3_steps, "warmup": warm, "ms_per_step": ms / args.c3_steps,
+           "tiles": [ctx.get_tile(a) for a in range(3)], "segments": [ctx.get_segments(a) for a in range(3)],
+           "status": ctx.status_check(), "finite": bool(torch.isfinite(u).all().item()),
+           "fp32_vs_fp64_after_steps": warm + args.c3_steps, "fp32_vs_fp64": err}
+    del u, u64
+    return out
 
 
 def main():
@@ -304,9 +467,12 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-series", action="store_true")
-    ap.add_argument("--harvest-steps", type=int, default=20)
+    ap.add_argument("--no-c3", action="store_true", help="skip the 512x384x384 leg")
+    ap.add_argument("--c3-steps", type=int, default=20)
+    ap.add_argument("--harvest-steps", type=int, default=105,
+                    help="plain steps whose interfaces are harvested (~96k records per step: 105 give 1e7)")
     ap.add_argument("--harvest-cap", type=int, default=10_000_000)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=6000)
     ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--tiles", type=str, default=None,
                     help="pencils per tile x,y,z for the FP32 run (with --segments: no autotuning)")
@@ -447,25 +613,27 @@ def main():
     bytes_per_launch = 64.0 * zones            # 8 FP32 variables read + written
     gbs = bytes_per_launch / (avg[dom] / 1000.0) / 1e9
     traffic, _ = load_traffic("f32")
-    flops_zone = FLOPS_PER_ZONE_SWEEP
-    if traffic and traffic.get("fp32_ops_per_lane"):
-        flops_zone = round(min(traffic["fp32_ops_per_lane"].values()), 1)
+    flops_zone, flops_src = FLOPS_PER_ZONE_SWEEP, FLOPS_SOURCE
     tflops = flops_zone * zones / (avg[dom] / 1000.0) / 1e12
     roofline = {
-        "bound": "alu",
-        "achieved": round(tflops, 2),
-        "peak": FP32_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+        "bound": "hbm",
+        "achieved": round(gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4),
         "traffic": traffic["bytes_per_launch"][str(dom)] if traffic else None,
         "kernel": f"sweep axis {'xyz'[dom]} (f32)",
-        "flops_per_zone_sweep": flops_zone,
-        "frac_of_unpacked_fp32": round(tflops / FP32_UNPACKED_TFLOPS, 4),
-        "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": bytes_per_launch},
+        "bytes_per_zone_sweep": 64,
+        "algorithmic_bytes_per_launch": bytes_per_launch,
         "avg_launch_ms": [round(a, 4) for a in avg],
         "launches": kn,
         "sum_kernel_ms_per_step": round(sum(kms) / args.steps, 4),
+        "limiter": "vector-ALU issue and latency, not HBM (the counter summaries in profiles/)",
+        "alu": {"achieved": round(tflops, 2), "peak": FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / FP32_UNPACKED_TFLOPS, 4),
+                "frac_of_packed_fp32_peak": round(tflops / FP32_PEAK_TFLOPS, 4),
+                "flops_per_zone_sweep": flops_zone, "flops_source": flops_src,
+                "kernel_fp32_ops_per_lane": KERNEL_FP32_OPS_PER_LANE},
     }
     out = {
         "metric": "zone-updates/s per 3D split step (FP32/learned vs FP64 plain) at stated error; HBM GB/s",
@@ -493,13 +661,26 @@ def main():
         "health": {"status": status, "finite": finite, "floor_hits": st["floor_hits"],
                    "nonconverged": st["nonconverged"], "simulated_time": ctx.time(u)},
     }
+    if not args.no_fp64:
+        # FP64 run of the same workload and step count (untimed) for the error
+        # of the FP32 headline run
+        print(f"[bench] fp64 reference run: {args.warmup + args.steps} steps", file=sys.stderr, flush=True)
+        ctx_r = make_ctx()
+        u_r = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float64).contiguous()
+        ctx_r.advance(u_r, args.warmup + args.steps, args.cfl)
+        torch.cuda.synchronize()
+        out["fp32_vs_fp64"] = fp32_vs_fp64(ctx, u, ctx_r, u_r)
+        out["fp32_vs_fp64"]["after_steps"] = args.warmup + args.steps
     if not args.no_series:
         print("[bench] inflow time series", file=sys.stderr, flush=True)
         out["inflow_series"] = series_leg(args, setup, make_ctx, ctx)
         torch.cuda.empty_cache()
     if not args.no_learned:
-        out["learned"] = learned_leg(args, setup, make_ctx, u, st, value)
+        out["learned"] = learned_leg(args, setup, make_ctx, u, st, value,
+                                     ref64=None if args.no_fp64 else (ctx_r, u_r))
         torch.cuda.empty_cache()
+    if not args.no_fp64:
+        del u_r, ctx_r
     del u
     torch.cuda.empty_cache()
 
@@ -519,6 +700,16 @@ def main():
 
     if not args.no_ensemble:
         out["ensemble"] = ensemble_leg(args)
+        torch.cuda.empty_cache()
+
+    if not args.no_c3:
+        def make_ctx_for(st):
+            c = ppmlr.Context(st.faces, st.bc_lo, st.bc_hi, r_inner=st.r_inner, p_floor=st.p_floor)
+            c.set_dipole(st.moment, st.direction)
+            c.set_inflow(st.inflow)
+            c.set_inner(st.inner_rho, st.inner_p)
+            return c
+        out["c3_512x384x384"] = c3_leg(args, make_ctx_for)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:

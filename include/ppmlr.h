@@ -64,7 +64,32 @@ typedef struct {
     int collect_stats;  /* iteration histogram and floor counters, 1 (about
                            2 % of a sweep's time) */
     int debug_cfl;      /* ppmlr_step checks dt against the CFL limit, 0 */
+    int tracing;        /* zone-edge values and interface solve (Section II:
+                           edge values by a characteristic method, then the
+                           interface Riemann problem), 0:
+                             PPMLR_TRACE_TWO_FAMILY (default): the fast pair
+                             (rho, u, p, B_t) and the Alfven pair (rho, v_t,
+                             B_t) traced over their own domains of
+                             dependence, with the oblique coupling terms;
+                             the two-shock Newton solve and the linear Alfven
+                             solve;
+                             PPMLR_TRACE_CHARACTERISTIC: the seven waves
+                             traced one by one (fast reference, Alfven and
+                             slow projected on their eigenvectors) and the
+                             interface problem of all seven waves in its
+                             linearisation about the face-mean state (no
+                             iteration; meant for smooth flows: it does not
+                             take the two-shock solve's nonlinear jumps).
+                             An Alfven or slow wave slower than 1e-4 of the
+                             fast wave counts as at rest (a normal field
+                             that cancels to rounding noise decides
+                             nothing); a traced state without positive
+                             density and pressure falls back to the zone
+                             average.
+                           Plain initial-guess mode only; no ensembles. */
 } ppmlr_options;
+#define PPMLR_TRACE_TWO_FAMILY 0
+#define PPMLR_TRACE_CHARACTERISTIC 1
 
 /* Grid: zone counts, boundary conditions, inner boundary radius. */
 typedef struct {
@@ -233,10 +258,20 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, 
  * own inflow and its own CFL-limited dt (the Section IV-A set-up per member),
  * advanced together.  Advances member m (ctxs[m], states[m]) by `steps` split
  * steps with dt computed on the device per member, exactly as ppmlr_advance
- * would (same arithmetic, bitwise equal results for the same tiles).  Each
- * sweep of a step is one launch that covers the tiles of every member, so
- * the device sees one large grid instead of many small ones; per step there
- * are four launches (per-member dt + three sweeps) whatever the member count.
+ * would (same arithmetic, bitwise equal results for the same tiles).  Two
+ * launch forms (ppmlr_set_ensemble_launch), with the same results:
+ *   - per sweep (default): each sweep of a step is one launch over the
+ *     tiles of every member (four launches per step: per-member dt + three
+ *     sweeps);
+ *   - persistent: the whole call is one launch; as many workgroups as the
+ *     device holds at once take the tiles of every member in each sweep,
+ *     with a grid-wide barrier between the phases (the start-of-call
+ *     signal-speed maximum, each step's per-member dt, each sweep).  The
+ *     launch is cooperative, so the runtime refuses a grid that cannot be
+ *     co-resident; a barrier wait that polls for seconds gives up, and the
+ *     call then returns PPMLR_EDEVICE.  Slower on MI355X (its kernel holds
+ *     more registers, so fewer workgroups are resident), kept for callers
+ *     that need one launch per call.
  * All states must share one dtype and stream (states[0]->stream) and all
  * contexts the same step-counter parity; the contexts' dt, time, signal-speed
  * and counter buffers are used as by ppmlr_advance, so none of the contexts
@@ -253,6 +288,19 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *ctx, const ppmlr_state *state, int reps, 
  * work tables. */
 ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
                                 double cfl, int block, ppmlr_status *per_member);
+
+/* Launch form of the ensemble calls (process-wide; default per sweep).
+ * EINVAL for another value. */
+#define PPMLR_ENSEMBLE_PERSISTENT 0
+#define PPMLR_ENSEMBLE_PER_SWEEP 1
+ppmlr_status ppmlr_set_ensemble_launch(int mode);
+
+/* Polls of a grid-barrier wait in the persistent ensemble launch before it
+ * gives up (process-wide; default 4194304, seconds of waiting).  0 makes
+ * every wait give up at its first poll, which exercises the error path
+ * (PPMLR_EDEVICE, the kernel leaves normally, the states are then
+ * undefined).  EINVAL for a negative value. */
+ppmlr_status ppmlr_set_ensemble_barrier_limit(long long polls);
 
 /* Ensemble tile autotuner: times `reps` ensemble steps for each feasible
  * workgroup size (256, 512, 1024) and target segment length (whole pencils,

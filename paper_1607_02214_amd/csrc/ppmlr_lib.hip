@@ -336,14 +336,14 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, const T *in, T *u, in
     a.harvest_count = c->harvest_count;
 }
 
-template <int AX, typename T, bool STATS, bool FUSE, int SM, int GUESS = 0>
+template <int AX, typename T, bool STATS, bool FUSE, int SM, int GUESS = 0, bool TRACE = false>
 ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
 {
     const int threads = block_threads(a.P, a.M);
     const int slots = (GUESS == ppmlr::kGuessPlain ? kSlotsA : ppmlr::kSlotsAGuess) + kSlotsB;
     const size_t lds = ppmlr::lds_bytes(slots, SM > 0 ? SM : a.S, (int)sizeof(T));
     const int blocks = 8 * a.tiles_per_xcd;
-    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM, GUESS>;
+    auto kern = ppmlr::sweep_kernel<AX, T, STATS, FUSE, SM, GUESS, TRACE>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute");
@@ -352,21 +352,21 @@ ppmlr_status launch_one(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t 
     return hip_check(c, hipGetLastError(), "sweep launch");
 }
 
-template <int AX, typename T, bool STATS, bool FUSE>
+template <int AX, typename T, bool STATS, bool FUSE, bool TRACE = false>
 ppmlr_status launch_sm(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st)
 {
     switch (stride_for(block_threads(a.P, a.M), (int)sizeof(T))) {
-    case 256: return launch_one<AX, T, STATS, FUSE, 256>(c, a, st);
-    case 384: return launch_one<AX, T, STATS, FUSE, 384>(c, a, st);
-    case 512: return launch_one<AX, T, STATS, FUSE, 512>(c, a, st);
-    case 640: return launch_one<AX, T, STATS, FUSE, 640>(c, a, st);
-    case 768: return launch_one<AX, T, STATS, FUSE, 768>(c, a, st);
-    case 896: return launch_one<AX, T, STATS, FUSE, 896>(c, a, st);
+    case 256: return launch_one<AX, T, STATS, FUSE, 256, 0, TRACE>(c, a, st);
+    case 384: return launch_one<AX, T, STATS, FUSE, 384, 0, TRACE>(c, a, st);
+    case 512: return launch_one<AX, T, STATS, FUSE, 512, 0, TRACE>(c, a, st);
+    case 640: return launch_one<AX, T, STATS, FUSE, 640, 0, TRACE>(c, a, st);
+    case 768: return launch_one<AX, T, STATS, FUSE, 768, 0, TRACE>(c, a, st);
+    case 896: return launch_one<AX, T, STATS, FUSE, 896, 0, TRACE>(c, a, st);
     case 1024:
-        if constexpr (sizeof(T) == 4) return launch_one<AX, T, STATS, FUSE, 1024>(c, a, st);
+        if constexpr (sizeof(T) == 4) return launch_one<AX, T, STATS, FUSE, 1024, 0, TRACE>(c, a, st);
         else return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
     case 0:
-        if constexpr (sizeof(T) == 8) return launch_one<AX, T, STATS, FUSE, 0>(c, a, st);
+        if constexpr (sizeof(T) == 8) return launch_one<AX, T, STATS, FUSE, 0, 0, TRACE>(c, a, st);
         else return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
     default: return fail(c, PPMLR_EINVAL, "tile does not fit the LDS");
     }
@@ -388,6 +388,12 @@ ppmlr_status launch_guess(ppmlr_ctx *c, const ppmlr::SweepArgs<float> &a, hipStr
 template <int AX, typename T>
 ppmlr_status launch_axis(ppmlr_ctx *c, const ppmlr::SweepArgs<T> &a, hipStream_t st, bool stats, bool fuse)
 {
+    if (c->opt.tracing == PPMLR_TRACE_CHARACTERISTIC) {
+        // counters always collected in the kernel (not stored without a buffer)
+        if (c->guess != PPMLR_GUESS_PLAIN)
+            return fail(c, PPMLR_EINVAL, "the characteristic mode takes the plain interface solve");
+        return fuse ? launch_sm<AX, T, true, true, true>(c, a, st) : launch_sm<AX, T, true, false, true>(c, a, st);
+    }
     if constexpr (sizeof(T) == 4) {
         if (c->guess == PPMLR_GUESS_LEARNED)
             return fuse ? launch_guess<AX, true, ppmlr::kGuessLearned>(c, a, st)
@@ -543,9 +549,45 @@ __device__ inline void bg64(double dip_m, const double *dir, const double *bext,
     }
 }
 
+// Signal speed of zone z outside the inner boundary (0 inside): max_a
+// (|v_a| + c_f,a) / dx_a in FP64.
+template <typename T>
+__device__ inline double cfl_zone(const CflArgs<T> &a, long long z)
+{
+    int i = (int)(z % a.nx);
+    int j = (int)((z / a.nx) % a.ny);
+    int k = (int)(z / ((long long)a.nx * a.ny));
+    double x = a.xc[i], y = a.yc[j], zz = a.zc[k];
+    if (a.has_inner && x * x + y * y + zz * zz < a.r_inner2) return 0.0;
+    double r = (double)a.u[z];
+    double vx = (double)a.u[a.vol + z] / r, vy = (double)a.u[2 * a.vol + z] / r, vz = (double)a.u[3 * a.vol + z] / r;
+    double px = (double)a.u[4 * a.vol + z], py = (double)a.u[5 * a.vol + z], pz = (double)a.u[6 * a.vol + z];
+    double p = (a.gamma - 1.0) * ((double)a.u[7 * a.vol + z] - 0.5 * r * (vx * vx + vy * vy + vz * vz) -
+                                  0.5 * (px * px + py * py + pz * pz));
+    if (p < a.p_floor) p = a.p_floor;
+    double bx, by, bz;
+    bg64(a.dip_m, a.dir, a.bext, x, y, zz, bx, by, bz);
+    bx += px; by += py; bz += pz;
+    double a2 = a.gamma * p / r;
+    double b2 = (bx * bx + by * by + bz * bz) / r;
+    double w[3] = {a.dx[i], a.dy[j], a.dz[k]};
+    double v[3] = {vx, vy, vz};
+    double B[3] = {bx, by, bz};
+    double smax = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double ba2 = B[c] * B[c] / r;
+        double disc = (a2 + b2) * (a2 + b2) - 4.0 * a2 * ba2;
+        disc = disc > 0.0 ? disc : 0.0;
+        double cf = __builtin_sqrt(0.5 * (a2 + b2 + __builtin_sqrt(disc)));
+        double s = (__builtin_fabs(v[c]) + cf) / w[c];
+        smax = s > smax ? s : smax;
+    }
+    return smax;
+}
+
 // Signal-speed maximum over all zones outside the inner boundary: per zone
-// max_a (|v_a| + c_f,a) / dx_a in FP64; wave shuffles, then one atomic per
-// workgroup on the bits of the (non-negative) double.
+// cfl_zone; wave shuffles, then one atomic per workgroup on the bits of the
+// (non-negative) double.
 template <typename T>
 __global__ void __launch_bounds__(256) cfl_kernel(const CflArgs<T> a)
 {
@@ -553,33 +595,8 @@ __global__ void __launch_bounds__(256) cfl_kernel(const CflArgs<T> a)
     double smax = 0.0;
     for (long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x; z < a.vol;
          z += (long long)gridDim.x * blockDim.x) {
-        int i = (int)(z % a.nx);
-        int j = (int)((z / a.nx) % a.ny);
-        int k = (int)(z / ((long long)a.nx * a.ny));
-        double x = a.xc[i], y = a.yc[j], zz = a.zc[k];
-        if (a.has_inner && x * x + y * y + zz * zz < a.r_inner2) continue;
-        double r = (double)a.u[z];
-        double vx = (double)a.u[a.vol + z] / r, vy = (double)a.u[2 * a.vol + z] / r, vz = (double)a.u[3 * a.vol + z] / r;
-        double px = (double)a.u[4 * a.vol + z], py = (double)a.u[5 * a.vol + z], pz = (double)a.u[6 * a.vol + z];
-        double p = (a.gamma - 1.0) * ((double)a.u[7 * a.vol + z] - 0.5 * r * (vx * vx + vy * vy + vz * vz) -
-                                      0.5 * (px * px + py * py + pz * pz));
-        if (p < a.p_floor) p = a.p_floor;
-        double bx, by, bz;
-        bg64(a.dip_m, a.dir, a.bext, x, y, zz, bx, by, bz);
-        bx += px; by += py; bz += pz;
-        double a2 = a.gamma * p / r;
-        double b2 = (bx * bx + by * by + bz * bz) / r;
-        double w[3] = {a.dx[i], a.dy[j], a.dz[k]};
-        double v[3] = {vx, vy, vz};
-        double B[3] = {bx, by, bz};
-        for (int c = 0; c < 3; ++c) {
-            double ba2 = B[c] * B[c] / r;
-            double disc = (a2 + b2) * (a2 + b2) - 4.0 * a2 * ba2;
-            disc = disc > 0.0 ? disc : 0.0;
-            double cf = __builtin_sqrt(0.5 * (a2 + b2 + __builtin_sqrt(disc)));
-            double s = (__builtin_fabs(v[c]) + cf) / w[c];
-            smax = s > smax ? s : smax;
-        }
+        const double s = cfl_zone(a, z);
+        smax = s > smax ? s : smax;
     }
     for (int off = 32; off > 0; off >>= 1) {
         double o = __shfl_xor(smax, off);
@@ -717,7 +734,7 @@ __global__ void totals_final(const double *partials, int nblocks, double *out)
 }
 
 template <typename T>
-ppmlr_status cfl_typed(ppmlr_ctx *c, const T *u, hipStream_t st)
+CflArgs<T> cfl_args(const ppmlr_ctx *c, const T *u)
 {
     CflArgs<T> a;
     a.u = u;
@@ -732,6 +749,13 @@ ppmlr_status cfl_typed(ppmlr_ctx *c, const T *u, hipStream_t st)
     a.dip_m = c->dip_m;
     for (int k = 0; k < 3; ++k) { a.dir[k] = c->dir[k]; a.bext[k] = c->bext[k]; }
     a.out = c->d_cflmax;
+    return a;
+}
+
+template <typename T>
+ppmlr_status cfl_typed(ppmlr_ctx *c, const T *u, hipStream_t st)
+{
+    const CflArgs<T> a = cfl_args(c, u);
     long long blocks = (a.vol + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(cfl_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, a);
@@ -763,6 +787,7 @@ void ppmlr_default_options(ppmlr_options *o)
     o->p_floor = 1e-8;
     o->collect_stats = 1;
     o->debug_cfl = 0;
+    o->tracing = PPMLR_TRACE_TWO_FAMILY;
 }
 
 ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coords *coords,
@@ -793,7 +818,8 @@ ppmlr_status ppmlr_create(const ppmlr_grid *grid, double gamma, const ppmlr_coor
     c->gamma = gamma;
     if (opt) c->opt = *opt;
     else ppmlr_default_options(&c->opt);
-    if (c->opt.max_iter < 0 || !(c->opt.tol_f64 > 0) || !(c->opt.tol_f32 > 0)) {
+    if (c->opt.max_iter < 0 || !(c->opt.tol_f64 > 0) || !(c->opt.tol_f32 > 0) ||
+        (c->opt.tracing != PPMLR_TRACE_TWO_FAMILY && c->opt.tracing != PPMLR_TRACE_CHARACTERISTIC)) {
         delete c;
         return PPMLR_EINVAL;
     }
@@ -1284,7 +1310,13 @@ ppmlr_status ppmlr_autotune(ppmlr_ctx *c, const ppmlr_state *s, int reps, int ti
 
 namespace {
 
+// Polls of a barrier wait before it gives up, by default (each poll is an
+// agent-scope load plus a short sleep, well above a microsecond: seconds in
+// all, against milliseconds for the longest sweep of an ensemble).
+constexpr long long kBarSpinLimit = 1ll << 22;
 int g_ensemble_block = 0;   // set by ppmlr_ensemble_autotune
+int g_ensemble_launch = PPMLR_ENSEMBLE_PER_SWEEP;    // set by ppmlr_set_ensemble_launch
+long long g_ensemble_barrier_polls = kBarSpinLimit;  // set by ppmlr_set_ensemble_barrier_limit
 
 // dt of every member from its signal-speed maximum, exactly as dt_kernel
 // (one wave of kCflSlots threads per member)
@@ -1302,9 +1334,225 @@ __global__ void ens_dt_kernel(unsigned long long *const *smax_bits, double *cons
     *t[m] += d;
 }
 
+// Device work tables of one ensemble call: the sweep descriptors (3 axes x 2
+// buffer parities x members), the tile offsets (3 axes x (members + 1)), the
+// per-member signal-speed / dt / time pointers (3 x members), the members'
+// signal-speed arguments and the barrier words of the persistent launch,
+// each part starting on a 256-byte boundary.
+// ---------------------------------------------------------------- persistent ensemble
+
+// Barrier words of one persistent launch, each on its own 256-byte line:
+// arrival count, generation, status (0 = running, 1 = a barrier wait gave
+// up); then the tile counters of the sweeps, two sets (sweeps alternate
+// between them) of one counter per XCD, 256 bytes apart.
+constexpr int kBarCount = 0, kBarGen = 64, kBarStatus = 128, kBarTiles = 192, kBarWords = kBarTiles + 2 * 8 * 64;
+
+// Grid-wide barrier of a co-resident grid (cooperative launch).  Every
+// workgroup's writes before the barrier are visible to every workgroup after
+// it: the workgroup barrier orders the workgroup's writes before thread 0's
+// agent-scope release (which on a multi-XCD device writes dirty L2 lines
+// back), and thread 0's agent-scope acquire after the wait invalidates the
+// stale lines of its CU and XCD before any thread reads.  A wait that sees
+// the status set, or polls `limit` times, gives up: it sets the status
+// and returns false, and so does every later barrier, so all workgroups
+// leave the kernel.  gen: this workgroup's count of barriers passed; s_ok:
+// one LDS word of the workgroup.
+__device__ bool grid_barrier(unsigned int *bar, unsigned int nblocks, unsigned int &gen, unsigned int *s_ok,
+                             long long limit)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned int target = gen + 1;
+        __threadfence();
+        const unsigned int prev =
+            __hip_atomic_fetch_add(&bar[kBarCount], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nblocks - 1) {
+            // last to arrive: reset the count, then open the next generation
+            __hip_atomic_store(&bar[kBarCount], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[kBarGen], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long polls = 0;
+            while (__hip_atomic_load(&bar[kBarGen], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+                if (__hip_atomic_load(&bar[kBarStatus], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    ++polls > limit) {
+                    __hip_atomic_store(&bar[kBarStatus], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (ok && __hip_atomic_load(&bar[kBarStatus], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
+        __threadfence();
+        gen = target;
+        *s_ok = (unsigned int)ok;
+    }
+    __syncthreads();
+    return *s_ok != 0u;
+}
+
+template <typename T>
+struct PersistArgs {
+    const ppmlr::SweepArgs<T> *desc;   // [3 axes][2 buffer parities][members]
+    const int *mo;                     // [3][members + 1] tile offsets
+    const CflArgs<T> *cfla;            // [members]: the start-of-call signal-speed maximum
+    unsigned long long *const *smax;   // [members] signal-speed slots
+    double *const *dt;                 // [members] device dt
+    double *const *t;                  // [members] simulated time
+    unsigned int *bar;                 // barrier words (kBarWords, zero at launch)
+    long long barrier_polls;           // polls of a barrier wait before it gives up
+    int members, steps;
+    int odd0;                          // the first step runs z, y, x
+    double cfl;
+};
+
+// One persistent launch for a whole ensemble call.  Phases, separated by
+// grid barriers: clear the members' signal-speed slots; the start-of-call
+// maximum of every member (the arithmetic of cfl_kernel); then per step the
+// members' dt (the arithmetic of dt_kernel) and the step's three sweeps over
+// the tiles of all members (sweep_tile, exactly as in ensemble_sweep_kernel;
+// the last sweep of a step also collects the next maximum).  The tiles of a
+// sweep are cut into 8 consecutive shares in the order of the
+// one-launch-per-sweep kernel, share x for the workgroups of XCD x (b mod 8;
+// G is a multiple of 8), so that neighbouring tiles meet in one L2; within
+// its share a workgroup claims the next tile from the XCD's counter, which
+// balances tiles of unequal cost.  The grid must be co-resident: it is
+// launched cooperatively.
+template <typename T, bool STATS, int SM>
+__global__ void __launch_bounds__(SM) ensemble_persistent_kernel(const PersistArgs<T> p)
+{
+    // all LDS is the dynamic allocation (tile buffers at address 0, then the
+    // workgroup's scalars: per-wave maxima, counters, the barrier flag)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    unsigned char *tail = smem_raw + ppmlr::lds_tile_bytes(kSlotsA + kSlotsB, SM, (int)sizeof(T));
+    double *s_red = reinterpret_cast<double *>(tail);
+    unsigned int *s_stat = reinterpret_cast<unsigned int *>(tail + 16 * sizeof(double));
+    unsigned int *s_ok = s_stat + ppmlr::kStatWords;
+    double *cred = s_red;
+    const int b = blockIdx.x;
+    const unsigned int G = gridDim.x;
+    unsigned int gen = 0;
+    const int n = p.members;
+    // slots cleared
+    for (int m = b; m < n; m += (int)G)
+        if (threadIdx.x < ppmlr::kCflSlots) p.smax[m][threadIdx.x * ppmlr::kCflStride] = 0ull;
+    if (!grid_barrier(p.bar, G, gen, s_ok, p.barrier_polls)) return;
+    // start-of-call signal-speed maximum of every member
+    for (int m = 0; m < n; ++m) {
+        const CflArgs<T> &ca = p.cfla[m];
+        double smax = 0.0;
+        for (long long z = (long long)b * SM + threadIdx.x; z < ca.vol; z += (long long)G * SM) {
+            const double s = cfl_zone(ca, z);
+            smax = s > smax ? s : smax;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(smax, off);
+            smax = o > smax ? o : smax;
+        }
+        if (__lane_id() == 0) cred[threadIdx.x >> 6] = smax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mx = cred[0];
+            for (int w = 1; w < SM / 64; ++w) mx = cred[w] > mx ? cred[w] : mx;
+            atomicMax(p.smax[m] + (b % ppmlr::kCflSlots) * ppmlr::kCflStride,
+                      (unsigned long long)__double_as_longlong(mx));
+        }
+        __syncthreads();
+    }
+    if (!grid_barrier(p.bar, G, gen, s_ok, p.barrier_polls)) return;
+    static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    long long j = 0;                                   // sweeps done in this call
+    for (int s = 0; s < p.steps; ++s) {
+        // dt of every member from its maximum; the slots are cleared for the next one
+        for (int m = b; m < n; m += (int)G) {
+            if (threadIdx.x < 64) {
+                const unsigned long long bits = slot_max(p.smax[m]);
+                p.smax[m][threadIdx.x * ppmlr::kCflStride] = 0ull;
+                if (threadIdx.x == 0) {
+                    const double smx = __longlong_as_double((long long)bits);
+                    const double d = smx > 0.0 ? p.cfl / smx : 0.0;
+                    *p.dt[m] = d;
+                    *p.t[m] += d;
+                }
+            }
+        }
+        if (!grid_barrier(p.bar, G, gen, s_ok, p.barrier_polls)) return;
+        const int *ord = ((p.odd0 + s) % 2 == 0) ? even : odd;
+        for (int k = 0; k < 3; ++k, ++j) {
+            const int ax = ord[k];
+            const ppmlr::SweepArgs<T> *desc = p.desc + ((size_t)ax * 2 + (size_t)(j & 1)) * n;
+            const int *mo = p.mo + (size_t)ax * (n + 1);
+            const int total = mo[n];
+            const int per_xcd = (total + 7) / 8;
+            const int xcd = b & 7;
+            unsigned int *ctr = p.bar + kBarTiles + ((j & 1) * 8 + xcd) * 64;
+            // the other set is free (its sweep ended before the last barrier)
+            // and is cleared for the next sweep, before the barrier after this one
+            if (b < 8 && threadIdx.x == 0)
+                __hip_atomic_store(p.bar + kBarTiles + (((j + 1) & 1) * 8 + b) * 64, 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            const int lo_t = xcd * per_xcd, hi_t = min(total, lo_t + per_xcd);
+            for (;;) {
+                if (threadIdx.x == 0)
+                    s_ok[1] = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                const int jt = lo_t + (int)s_ok[1];
+                __syncthreads();                      // the claim word is reused by the next claim
+                if (jt >= hi_t) break;
+                int lo = 0, hi = n - 1;               // largest m with mo[m] <= jt
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (mo[mid] <= jt) lo = mid; else hi = mid - 1;
+                }
+                const ppmlr::SweepArgs<T> &a = desc[lo];
+                const int t = jt - mo[lo];
+                int seg, tt;
+                if (a.seg_fast) { seg = t % a.nseg; tt = t / a.nseg; }
+                else { seg = t / a.ntiles; tt = t - seg * a.ntiles; }
+                const int tq = tt % a.tiles_q;
+                const int r = tt / a.tiles_q;
+                const T dtm = T(*a.dt_dev);
+                unsigned long long *cm =
+                    (k == 2 && a.cfl_max) ? a.cfl_max + (b % ppmlr::kCflSlots) * ppmlr::kCflStride : nullptr;
+                if (ax == 0)
+                    ppmlr::sweep_tile<0, T, STATS, true, SM>(a, tq, r, seg, dtm, cm, b % kStatSlots, smem_raw, s_red,
+                                                             s_stat);
+                else if (ax == 1)
+                    ppmlr::sweep_tile<1, T, STATS, true, SM>(a, tq, r, seg, dtm, cm, b % kStatSlots, smem_raw, s_red,
+                                                             s_stat);
+                else
+                    ppmlr::sweep_tile<2, T, STATS, true, SM>(a, tq, r, seg, dtm, cm, b % kStatSlots, smem_raw, s_red,
+                                                             s_stat);
+                __syncthreads();                      // the tile buffers are reused by the next tile
+            }
+            if (!grid_barrier(p.bar, G, gen, s_ok, p.barrier_polls)) return;
+        }
+    }
+}
+
+template <typename T>
+struct EnsTables {
+    static constexpr size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+    static constexpr size_t desc_bytes(int n) { return up256(sizeof(ppmlr::SweepArgs<T>) * 6 * (size_t)n); }
+    static constexpr size_t mo_bytes(int n) { return up256(sizeof(int) * 3 * ((size_t)n + 1)); }
+    static constexpr size_t ptr_bytes(int n) { return up256(sizeof(void *) * 3 * (size_t)n); }
+    static constexpr size_t cfl_bytes(int n) { return up256(sizeof(CflArgs<T>) * (size_t)n); }
+    static constexpr size_t bar_bytes() { return up256(sizeof(unsigned int) * kBarWords); }
+    static constexpr size_t bytes(int n)
+    {
+        return desc_bytes(n) + mo_bytes(n) + ptr_bytes(n) + cfl_bytes(n) + bar_bytes();
+    }
+};
+
+// One ensemble call.  tables: device memory of EnsTables<T>::bytes(n) for
+// the work tables, or nullptr to allocate them for this call (and free them
+// at its end).  With tables given, nothing is allocated: a member whose
+// pencils are cut into segments must then already have its context's second
+// state.
 template <typename T>
 ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps, double cfl,
-                            int block)
+                            int block, unsigned char *tables = nullptr, bool persistent = true)
 {
     ppmlr_ctx *c0 = ctxs[0];
     hipStream_t st = (hipStream_t)states[0]->stream;
@@ -1316,7 +1564,13 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
     for (int m = 0; m < n; ++m) {
         for (int ax = 0; ax < 3; ++ax)
             if (seg_count(ctxs[m], ax, (int)sizeof(T)) > 1) pp[m] = 1;
-        if (pp[m]) {
+        if (pp[m] && tables) {
+            if (ctxs[m]->pong_bytes < state_bytes(ctxs[m], states[m]))
+                return fail(c0, PPMLR_EINVAL,
+                            "member " + std::to_string(m) + " is cut into pencil segments but its context has no "
+                            "second state yet (run it once through ppmlr_ensemble_run or sweep it, or use whole "
+                            "pencils)");
+        } else if (pp[m]) {
             ppmlr_status e = ensure_pong(ctxs[m], state_bytes(ctxs[m], states[m]));
             if (e) return e;
         }
@@ -1348,20 +1602,23 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         if (off > (long long)INT_MAX / 2) return fail(c0, PPMLR_EINVAL, "ensemble too large for one launch");
         mo[(size_t)ax * (n + 1) + n] = (int)off;
     }
-    std::vector<void *> allocs;
     ppmlr_status err = PPMLR_OK;
-    auto dalloc = [&](size_t bytes) -> void * {
-        void *p = nullptr;
-        if (!err) err = hip_check(c0, hipMalloc(&p, std::max<size_t>(bytes, 16)), "hipMalloc");
-        if (p) allocs.push_back(p);
-        return p;
-    };
+    unsigned char *owned = nullptr;
+    if (!tables) {
+        err = hip_check(c0, hipMalloc((void **)&owned, EnsTables<T>::bytes(n)), "hipMalloc");
+        tables = owned;
+    }
     auto up = [&](void *dst, const void *src, size_t bytes) {
         if (!err) err = hip_check(c0, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     };
-    auto *d_desc = (ppmlr::SweepArgs<T> *)dalloc(sizeof(ppmlr::SweepArgs<T>) * desc.size());
-    auto *d_mo = (int *)dalloc(sizeof(int) * mo.size());
-    auto *d_ptr = (void **)dalloc(sizeof(void *) * 3 * (size_t)n);
+    auto *d_desc = (ppmlr::SweepArgs<T> *)tables;
+    auto *d_mo = (int *)(tables + EnsTables<T>::desc_bytes(n));
+    auto *d_ptr = (void **)(tables + EnsTables<T>::desc_bytes(n) + EnsTables<T>::mo_bytes(n));
+    auto *d_cfl = (CflArgs<T> *)(tables + EnsTables<T>::desc_bytes(n) + EnsTables<T>::mo_bytes(n) +
+                                  EnsTables<T>::ptr_bytes(n));
+    auto *d_bar = (unsigned int *)((unsigned char *)d_cfl + EnsTables<T>::cfl_bytes(n));
+    std::vector<CflArgs<T>> cfla((size_t)n);
+    std::vector<unsigned int> bar0(kBarWords, 0u);
     if (!err) {
         std::vector<void *> ptr((size_t)3 * n);
         for (int m = 0; m < n; ++m) {
@@ -1372,15 +1629,81 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         up(d_desc, desc.data(), sizeof(ppmlr::SweepArgs<T>) * desc.size());
         up(d_mo, mo.data(), sizeof(int) * mo.size());
         up(d_ptr, ptr.data(), sizeof(void *) * ptr.size());
+        if (persistent) {
+            for (int m = 0; m < n; ++m) cfla[m] = cfl_args(ctxs[m], (const T *)states[m]->u);
+            up(d_cfl, cfla.data(), sizeof(CflArgs<T>) * cfla.size());
+            up(d_bar, bar0.data(), sizeof(unsigned int) * bar0.size());
+        }
         // the host tables must stay alive until the copies have been made
         if (!err) err = hip_check(c0, hipStreamSynchronize(st), "hipStreamSynchronize");
     }
-    // signal-speed maximum of every member's current state
-    for (int m = 0; m < n && !err; ++m) err = cfl_launch(ctxs[m], states[m]);
     const size_t lds = ppmlr::lds_bytes(kSlotsA + kSlotsB, block, (int)sizeof(T));
-    static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
     long long j = 0;                                       // sweeps enqueued by this call
-    for (int s = 0; s < steps && !err; ++s) {
+    if (persistent && !err) {
+        // one cooperative launch of as many workgroups as the device holds at
+        // once (the runtime refuses a grid that cannot be co-resident)
+        PersistArgs<T> pa;
+        pa.desc = d_desc;
+        pa.mo = d_mo;
+        pa.cfla = d_cfl;
+        pa.smax = (unsigned long long *const *)d_ptr;
+        pa.dt = (double *const *)(d_ptr + n);
+        pa.t = (double *const *)(d_ptr + 2 * (size_t)n);
+        pa.bar = d_bar;
+        pa.barrier_polls = g_ensemble_barrier_polls;
+        pa.members = n;
+        pa.steps = steps;
+        pa.odd0 = (int)(c0->step % 2);
+        pa.cfl = cfl;
+        int maxtiles = 8;
+        for (int ax = 0; ax < 3; ++ax) maxtiles = std::max(maxtiles, mo[(size_t)ax * (n + 1) + n]);
+        auto launch = [&](auto kern) {
+            if (lds > 64 * 1024) {
+                hipError_t he =
+                    hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (he != hipSuccess) { err = hip_check(c0, he, "hipFuncSetAttribute"); return; }
+            }
+            int per_cu = 0, cus = 0, coop = 0;
+            err = hip_check(c0, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds),
+                            "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            if (!err) err = hip_check(c0, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c0->device),
+                                      "hipDeviceGetAttribute");
+            if (!err) err = hip_check(c0, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c0->device),
+                                      "hipDeviceGetAttribute");
+            if (err) return;
+            if (!coop || per_cu < 1) { err = fail(c0, PPMLR_EDEVICE, "no cooperative launch for the ensemble kernel"); return; }
+            // a multiple of 8 (the XCD-aware tile order keeps each workgroup on its XCD's share)
+            long long G = (long long)per_cu * cus;
+            G = std::min<long long>(G, ((long long)maxtiles + 7) / 8 * 8);
+            G = std::max<long long>(8, G / 8 * 8);
+            void *args[] = {(void *)&pa};
+            err = hip_check(c0, hipLaunchCooperativeKernel((const void *)kern, dim3((unsigned)G), dim3(block), args,
+                                                           (unsigned)lds, st), "hipLaunchCooperativeKernel");
+        };
+#define PPMLR_PERS(B_)                                                                   \
+        if (stats) launch(ensemble_persistent_kernel<T, true, B_>);                       \
+        else launch(ensemble_persistent_kernel<T, false, B_>);
+        if (block == 256) { PPMLR_PERS(256) }
+        else if (block == 512) { PPMLR_PERS(512) }
+        else {
+            if constexpr (sizeof(T) == 4) { PPMLR_PERS(1024) }
+            else err = fail(c0, PPMLR_EINVAL, "FP64 ensembles use block 256 or 512");
+        }
+#undef PPMLR_PERS
+        unsigned int status = 0;
+        if (!err) err = hip_check(c0, hipMemcpyAsync(&status, d_bar + kBarStatus, sizeof(status),
+                                                     hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        if (!err) err = hip_check(c0, hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (!err && status != 0u)
+            err = fail(c0, PPMLR_EDEVICE, "ensemble kernel: a grid barrier wait gave up (workgroups not co-resident?)");
+        j = 3LL * steps;
+    }
+    // one launch per sweep: the start-of-call maximum, then per step the dt
+    // kernel and three sweep kernels
+    if (!persistent)
+        for (int m = 0; m < n && !err; ++m) err = cfl_launch(ctxs[m], states[m]);
+    static const int even[3] = {0, 1, 2}, odd[3] = {2, 1, 0};
+    for (int s = 0; s < steps && !err && !persistent; ++s) {
         hipLaunchKernelGGL(ens_dt_kernel, dim3(n), dim3(ppmlr::kCflSlots), 0, st, (unsigned long long *const *)d_ptr,
                            (double *const *)(d_ptr + n), (double *const *)(d_ptr + 2 * (size_t)n), n, cfl);
         const int *ord = ((c0->step + s) % 2 == 0) ? even : odd;
@@ -1426,9 +1749,11 @@ ppmlr_status ensemble_typed(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         if (pp[m])
             err = hip_check(c0, hipMemcpyAsync(states[m]->u, ctxs[m]->d_pong, state_bytes(ctxs[m], states[m]),
                                                hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-    // the device tables are freed once the launches that read them are done
-    (void)hipStreamSynchronize(st);
-    for (void *p : allocs) (void)hipFree(p);
+    // tables allocated here are freed once the launches that read them are done
+    if (owned) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(owned);
+    }
     return err;
 }
 
@@ -1444,6 +1769,8 @@ ppmlr_status ensemble_check(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
         if (states[m]->stream != states[0]->stream) return fail(ctxs[0], PPMLR_EINVAL, "members differ in stream");
         if ((ctxs[m]->step & 1) != (ctxs[0]->step & 1)) return fail(ctxs[0], PPMLR_EINVAL, "step parity differs");
         if (ctxs[m]->series_n > 0) return fail(ctxs[0], PPMLR_EINVAL, "inflow time series are not supported in ensembles");
+        if (ctxs[m]->opt.tracing != PPMLR_TRACE_TWO_FAMILY)
+            return fail(ctxs[0], PPMLR_EINVAL, "ensembles use the two-family tracing");
         const int elem = states[m]->dtype == PPMLR_F64 ? 8 : 4;
         for (int a = 0; a < 3; ++a)
             if (tile_M(ctxs[m], a, elem) > block)
@@ -1465,14 +1792,31 @@ ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const
     ppmlr_status e = ensemble_check(ctxs, states, n, steps, cfl, block);
     if (e) return e;
     if (steps > 0) {
-        e = states[0]->dtype == PPMLR_F64 ? ensemble_typed<double>(ctxs, states, n, steps, cfl, block)
-                                          : ensemble_typed<float>(ctxs, states, n, steps, cfl, block);
+        e = states[0]->dtype == PPMLR_F64
+                ? ensemble_typed<double>(ctxs, states, n, steps, cfl, block, nullptr,
+                                         g_ensemble_launch == PPMLR_ENSEMBLE_PERSISTENT)
+                : ensemble_typed<float>(ctxs, states, n, steps, cfl, block, nullptr,
+                                        g_ensemble_launch == PPMLR_ENSEMBLE_PERSISTENT);
         if (!e)
             for (int m = 0; m < n; ++m) ctxs[m]->step += steps;
     }
     if (per_member)
         for (int m = 0; m < n; ++m) per_member[m] = e ? e : ppmlr_status_check(ctxs[m], states[m]->stream);
     return e;
+}
+
+ppmlr_status ppmlr_set_ensemble_launch(int mode)
+{
+    if (mode != PPMLR_ENSEMBLE_PERSISTENT && mode != PPMLR_ENSEMBLE_PER_SWEEP) return PPMLR_EINVAL;
+    g_ensemble_launch = mode;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_set_ensemble_barrier_limit(long long polls)
+{
+    if (polls < 0) return PPMLR_EINVAL;
+    g_ensemble_barrier_polls = polls;
+    return PPMLR_OK;
 }
 
 ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int reps,

@@ -22,6 +22,7 @@
 // The pencil axis is a template parameter so that all component indexing is
 // static (no private arrays with dynamic indices).
 #pragma once
+#include "ppmlr_char.hpp"
 #include "ppmlr_mlp.hpp"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -44,11 +45,12 @@ constexpr int kStatSlots = 64;  // copies of the counters (workgroup b adds to c
 
 // Dynamic LDS of a sweep workgroup: the tile buffers A and B (slots values
 // per zone, stride S) from address 0, then the workgroup's scalars: 16
-// doubles of per-wave signal-speed maxima, the kStatWords counters and the
-// learned guess's face count.  With the buffers at address 0 a zone's LDS
+// doubles of per-wave signal-speed maxima, the kStatWords counters, the
+// learned guess's face count (or a persistent launch's barrier flag) and a
+// persistent launch's tile claim.  With the buffers at address 0 a zone's LDS
 // address is its lane offset, with the slot in the instruction's offset
 // field; behind static shared arrays every address needed their size added.
-constexpr int kLdsTail = 16 * 8 + (kStatWords + 1) * 4;
+constexpr int kLdsTail = 16 * 8 + (kStatWords + 2) * 4;
 __host__ __device__ constexpr size_t lds_tile_bytes(int slots, int S, int elem)
 {
     return ((size_t)slots * (size_t)S * (size_t)elem + 15) / 16 * 16;
@@ -397,7 +399,12 @@ __device__ inline bool guess_features(const T *L, const T *R, T gate_p, T gate_u
 // guess, the learned (MLP) guess on selected faces, or the plain guess with
 // the selected faces' states and solutions recorded for training.  s_guess:
 // one LDS counter (learned mode).
-template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain>
+// Margin of the shock detector's compression test, in sound speeds
+// sqrt(P / rho): no shock compresses by less, and a strict u_{j-1} > u_{j+1}
+// at a pressure jump at rest would let rounding noise decide flattening.
+constexpr double kCompMin = 1e-5;
+
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain, bool TRACE = false>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, const int r, const int seg, const T dt,
                                            unsigned long long *cfl_max, const int stat_slot,
                                            unsigned char *smem_raw, double *s_red, unsigned int *s_stat,
@@ -405,6 +412,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
 {
     static_assert(GUESS == kGuessPlain || (SM > 0 && sizeof(T) == 4 && STATS),
                   "learned / harvest modes are FP32 sweeps with a compile-time stride and counters");
+    static_assert(!TRACE || GUESS == kGuessPlain, "the characteristic mode takes the plain interface solve");
     const int S = SM > 0 ? SM : a.S;                      // LDS stride
     T *sA = reinterpret_cast<T *>(smem_raw);
     T *sB = sA + (GUESS == kGuessPlain ? kSlotsA : kSlotsAGuess) * S;
@@ -569,7 +577,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             T Pam = sA[10 * S + sm1], Pap = sA[10 * S + sp1];
             T um = sA[1 * S + sm1], up = sA[1 * S + sp1];
             T d1 = Ptp - Ptm, d2 = Ptp2 - Ptm2;
-            if (tabs(d1) > T(0.33) * tmin(Pap, Pam) && um > up) {
+            // compression with a margin of kCompMin sound speeds
+            // sqrt(P_min / rho), so that equal velocities (a pressure jump at
+            // rest) and rounding noise about them never flatten
+            const T pmin = tmin(Pap, Pam), du = um - up;
+            if (tabs(d1) > T(0.33) * pmin && du > T(0) && du * du * rho > T(kCompMin * kCompMin) * pmin) {
                 if (d2 != T(0)) ftil = tmax(T(0), tmin(T(1), T(10) * (Ar<T>::div(d1, d2) - T(0.75))));
                 else ftil = T(1);
             }
@@ -614,15 +626,67 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     const T dbn = (bnp - bnm) * Ar<T>::rcp(T(0.5) * dmm + dm + T(0.5) * dmp);
     const T ddn = (bfn - bln) * idm, dd1 = (bf1 - bl1) * idm, dd2 = (bf2 - bl2) * idm;
     const T dBn = ddn + dbn;
-    T corrP = hdt * rho * Bnc * (Bt1c * pDc[2] + Bt2c * pDc[3]) * idm;
-    T corrB1 = -hdt * rho * Bt1c * pDc[1] * idm;
-    T corrB2 = -hdt * rho * Bt2c * pDc[1] * idm;
+    // (the oblique-field terms are in the eigenvectors of the characteristic mode)
+    T corrP = TRACE ? T(0) : hdt * rho * Bnc * (Bt1c * pDc[2] + Bt2c * pDc[3]) * idm;
+    T corrB1 = TRACE ? T(0) : -hdt * rho * Bt1c * pDc[1] * idm;
+    T corrB2 = TRACE ? T(0) : -hdt * rho * Bt2c * pDc[1] * idm;
     const T corrU = hdt * (Bnc * dbn + bn * ddn);
     const T corrV1 = hdt * (b1 * dBn + bd1 * dbn + bn * dd1);
     const T corrV2 = hdt * (b2 * dBn + bd2 * dbn + bn * dd2);
     corrB1 += hdt * rho * (v1 * dBn - un * dd1);
     corrB2 += hdt * rho * (v2 * dBn - un * dd2);
     corrP += hdt * rho * ((Bt1c * v1 + Bt2c * v2) * dBn - un * (Bt1c * dd1 + Bt2c * dd2));
+
+    // Characteristic mode: the face states traced wave by wave.  The
+    // reference is the zone's parabola averaged over the fast wave's domain
+    // of dependence; the Alfven and slow waves moving into the face get their
+    // own averages (difference projected on the left eigenvector, taken out
+    // along the right one).  A traced state without positive density and
+    // pressure falls back to the zone average.  The split multi-D terms are
+    // added to u, v_t and B_t; the thermal pressure takes none (its
+    // Lagrangian equation has no term in dB_n/dm: corrP is the magnetic-
+    // pressure change B_t . corrB, which the corrected field carries into
+    // the interface total pressure).  The right-face state stays in
+    // registers, the left-face state goes to the zone on the left through
+    // LDS (slots 0..6).
+    T WLc[7];
+    if constexpr (TRACE) {
+        Waves7<T> wz;
+        wz.template init<Ar<T>>(rho, pth, gam, Bnc, Bt1c, Bt2c);
+        const T sp = rho * dt * idm;
+        const Frac<T> yf(tmin(T(1), wz.cf * sp)), ya(tmin(T(1), wz.ca * sp)), ys(tmin(T(1), wz.cs * sp));
+        const T corr[7] = {T(0), corrU, corrV1, corrV2, corrB1, corrB2, T(0)};
+        T WRc[7];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const T dir = side == 0 ? T(1) : T(-1);
+            T ref[7], DA[7], DS[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                if (side == 0) {
+                    ref[k] = avgR(pLc[k], pDc[k], p6c[k], yf);
+                    DA[k] = ref[k] - avgR(pLc[k], pDc[k], p6c[k], ya);
+                    DS[k] = ref[k] - avgR(pLc[k], pDc[k], p6c[k], ys);
+                } else {
+                    ref[k] = avgL(pLc[k], pDc[k], p6c[k], yf);
+                    DA[k] = ref[k] - avgL(pLc[k], pDc[k], p6c[k], ya);
+                    DS[k] = ref[k] - avgL(pLc[k], pDc[k], p6c[k], ys);
+                }
+            }
+            T bfa, baa, bsa, bfs, bas, bss;
+            wz.project(DA, dir, bfa, baa, bsa);
+            wz.project(DS, dir, bfs, bas, bss);
+            wz.add(ref, dir, T(0), wz.moves(wz.ca) ? -baa : T(0), wz.moves(wz.cs) ? -bss : T(0));
+            const bool phys = ref[0] > T(0) && ref[6] > T(0);
+            T *dst = side == 0 ? WLc : WRc;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) dst[k] = (phys ? ref[k] : W[k]) + corr[k];
+        }
+        if (slot_ok) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) sA[k * S + tid] = WRc[k];
+        }
+    }
 
     // interface states of this zone: L at its right face (i+1/2), R at its
     // left face (i-1/2); normal pair traced with y_n, Alfven pair with y_A
@@ -673,7 +737,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         if (Pt_ + Pd < T(0.5) * P0) Pt_ = T(0.5) * P0 - Pd;
         // k = (ge + 1) / (2 ge) with ge = C^2 / (rho P): 1/2 + rho P / (2 C^2)
         const T kh = T(0.5) * r_ * (Pt_ + Pd) * Ar<T>::rcp(C2) + T(0.5);
-        if (slot_ok) {
+        if (!TRACE && slot_ok) {
             sA[0 * S + tid] = Pt_;
             sA[1 * S + tid] = u_ + corrU;
             sA[2 * S + tid] = C;
@@ -761,7 +825,41 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
     if (!face_ok) {  // keep unused lanes trivial (no Newton iterations)
         RPt = LPt; Ru = Lu; RC = LC; Rk = Lk; Rr = Lr; Rv1 = Lv1; Rv2 = Lv2; Rb1 = Lb1; Rb2 = Lb2;
     }
-    T Pst, ust;
+    T Pst, ust, v1s, b1s, v2s, b2s;
+    const T bns = T(0.5) * (bn + bnp);
+    const T Bns = bfn + bns;
+    if constexpr (TRACE) {
+        // characteristic mode: the interface problem in its linearisation about
+        // the mean of the two traced states; the face state is the left state
+        // plus the waves of negative Lagrangian speed
+        T WRc[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) WRc[k] = face_ok ? sA[k * S + sp1] : WLc[k];
+        Waves7<T> wf;
+        wf.template init<Ar<T>>(T(0.5) * (WLc[0] + WRc[0]), T(0.5) * (WLc[6] + WRc[6]), gam, Bns,
+                                bf1 + T(0.5) * (WLc[4] + WRc[4]), bf2 + T(0.5) * (WLc[5] + WRc[5]));
+        T D[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) D[k] = WRc[k] - WLc[k];
+        T cfw, caw, csw;
+        wf.project(D, T(-1), cfw, caw, csw);
+        T Ws[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) Ws[k] = WLc[k];
+        wf.add(Ws, T(-1), wf.cf > T(0) ? cfw : T(0), wf.moves(wf.ca) ? caw : T(0), wf.moves(wf.cs) ? csw : T(0));
+        ust = Ws[1];
+        v1s = Ws[2];
+        v2s = Ws[3];
+        b1s = Ws[4];
+        b2s = Ws[5];
+        Pst = Ws[6] + bf1 * b1s + bf2 * b2s + T(0.5) * (b1s * b1s + b2s * b2s);
+        if (STATS) {
+            const bool counted = face_ok && g >= own_lo && g < gend;
+            wave_add(&s_stat[0], counted);          // no iteration
+            wave_add(&s_stat[32], cnt_floor);
+            wave_add(&s_stat[34], cnt_bad);
+        }
+    } else {
     {
         const T Pd = T(0.5) * (bf1 * bf1 + bf2 * bf2);
         const T PL = LPt + Pd, PR = RPt + Pd;
@@ -862,14 +960,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         }
     }
     // transverse pair: linear Alfven problem, increment form from the left
-    const T bns = T(0.5) * (bn + bnp);
-    const T Bns = bfn + bns;
     const T sig = tsgn(Bns);
     const T irs = Ar<T>::rcp(Lr + Rr);
-    const T v1s = Lv1 + (Rr * (Rv1 - Lv1) + sig * (Rb1 - Lb1)) * irs;
-    const T b1s = Lb1 + (Lr * (Rb1 - Lb1) + sig * Lr * Rr * (Rv1 - Lv1)) * irs;
-    const T v2s = Lv2 + (Rr * (Rv2 - Lv2) + sig * (Rb2 - Lb2)) * irs;
-    const T b2s = Lb2 + (Lr * (Rb2 - Lb2) + sig * Lr * Rr * (Rv2 - Lv2)) * irs;
+    v1s = Lv1 + (Rr * (Rv1 - Lv1) + sig * (Rb1 - Lb1)) * irs;
+    b1s = Lb1 + (Lr * (Rb1 - Lb1) + sig * Lr * Rr * (Rv1 - Lv1)) * irs;
+    v2s = Lv2 + (Rr * (Rv2 - Lv2) + sig * (Rb2 - Lb2)) * irs;
+    b2s = Lb2 + (Lr * (Rb2 - Lb2) + sig * Lr * Rr * (Rv2 - Lv2)) * irs;
+    }
     // Lagrangian fluxes in dipole + deviation flux form
     const T nn = bns * (bfn + T(0.5) * bns);
     const T Fpi = Pst - nn;
@@ -1008,7 +1105,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         const unsigned int o = base + (unsigned int)(g * (int)a.stride_n);
 #pragma unroll
         for (int v = 0; v < 8; ++v) elem(a.var[v], o) = out[v];
-        if (FUSE_CFL && !masked) {
+        if (FUSE_CFL && cfl_max && !masked) {
             // signal speed of the updated zone, for the next step's dt (the
             // maximum is reduced in FP64)
             int ix, iy, iz;
@@ -1061,8 +1158,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
         if (tid < kStatWords && s_stat[tid] != 0u && a.stats)
             atomicAdd(&a.stats[stat_slot * kStatWords + tid], (unsigned long long)s_stat[tid]);
     }
-    if (FUSE_CFL) {
+    if (FUSE_CFL && cfl_max) {
         // wave max (all lanes active), workgroup max, one atomic per workgroup
+        // (no target: a sweep that is not the last of its step in a launch
+        // that runs several)
         for (int off = 32; off > 0; off >>= 1) {
             T o = __shfl_xor(smax, off);
             smax = o > smax ? o : smax;
@@ -1082,7 +1181,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
 // the network pass next to the sweep's registers (~132 VGPRs, 3 waves per
 // SIMD); a budget of 4 waves per SIMD (128 registers, a few bytes spilled
 // in the fused form) makes it ~20 % faster (measured).
-template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain>
+template <int AX, typename T, bool STATS, bool FUSE_CFL, int SM, int GUESS = kGuessPlain, bool TRACE = false>
 __global__ void __launch_bounds__(SM > 0 ? SM : 1024)
     __attribute__((amdgpu_waves_per_eu(GUESS == kGuessLearned ? 4 : 1))) sweep_kernel(const SweepArgs<T> a)
 {
@@ -1107,7 +1206,7 @@ __global__ void __launch_bounds__(SM > 0 ? SM : 1024)
     const int tq = tile - r * a.tiles_q;
     const T dt = a.dt_dev ? T(*a.dt_dev) : a.dt;
     unsigned long long *cm = a.cfl_max ? a.cfl_max + (b % kCflSlots) * kCflStride : nullptr;
-    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS>(a, tq, r, seg, dt, cm, b % kStatSlots, smem_raw, s_red, s_stat,
+    sweep_tile<AX, T, STATS, FUSE_CFL, SM, GUESS, TRACE>(a, tq, r, seg, dt, cm, b % kStatSlots, smem_raw, s_red, s_stat,
                                                   s_guess);
 }
 

@@ -31,6 +31,7 @@ PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
 F32, F64 = 0, 1
 GHOSTS = 7
 GUESS_PLAIN, GUESS_LEARNED, GUESS_HARVEST = 0, 1, 2
+TRACE_TWO_FAMILY, TRACE_CHARACTERISTIC = 0, 1
 MLP_PARAMS = 5250
 RECORD_FLOATS = 28
 
@@ -54,6 +55,7 @@ class Options(C.Structure):
         ("p_floor", C.c_double),
         ("collect_stats", C.c_int),
         ("debug_cfl", C.c_int),
+        ("tracing", C.c_int),
     ]
 
 
@@ -125,6 +127,8 @@ SIGNATURES = {
     "ppmlr_autotune": (C.c_int, [_P, C.POINTER(State), C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_ensemble_run": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
                                      C.c_int, C.POINTER(C.c_int)]),
+    "ppmlr_set_ensemble_launch": (C.c_int, [C.c_int]),
+    "ppmlr_set_ensemble_barrier_limit": (C.c_int, [C.c_longlong]),
     "ppmlr_ensemble_autotune": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
                                           C.POINTER(C.c_int)]),
     "ppmlr_set_guess": (C.c_int, [_P, C.c_int, _P, _P]),
@@ -182,7 +186,10 @@ class Context:
             cd.faces[a] = self._faces[a].ctypes.data_as(_dp)
         g.r_inner = float(r_inner)
         opt = options if options is not None else default_options()
+        known = {f[0] for f in Options._fields_}
         for k, v in opt_overrides.items():
+            if k not in known:
+                raise TypeError(f"unknown option {k!r}")
             setattr(opt, k, v)
         self.options = opt
         self.n = tuple(g.n)
@@ -386,8 +393,9 @@ def _ensemble_args(ctxs, states, stream):
 
 
 def ensemble_run(ctxs, states, steps, cfl, block=0, stream=None):
-    """Advance every member (context, state tensor) by `steps` split steps in
-    one launch per sweep covering all members; returns the per-member status
+    """Advance every member (context, state tensor) by `steps` split steps,
+    all members in each launch (one launch per sweep, or one per call in the
+    persistent form, see set_ensemble_launch); returns the per-member status
     codes."""
     n, hs, sts, sp = _ensemble_args(ctxs, states, stream)
     per = (C.c_int * n)()
@@ -396,6 +404,25 @@ def ensemble_run(ctxs, states, steps, cfl, block=0, stream=None):
         msg = lib().ppmlr_last_error(ctxs[0].h)
         raise PPMLRError(rc, msg.decode() if msg else "")
     return list(per)
+
+
+ENSEMBLE_PERSISTENT, ENSEMBLE_PER_SWEEP = 0, 1
+
+
+def set_ensemble_launch(mode):
+    """Launch form of the ensemble calls: ENSEMBLE_PER_SWEEP (one launch per
+    sweep, the default) or ENSEMBLE_PERSISTENT (one launch per call)."""
+    rc = lib().ppmlr_set_ensemble_launch(int(mode))
+    if rc != PPMLR_OK:
+        raise PPMLRError(rc, "bad ensemble launch mode")
+
+
+def set_ensemble_barrier_limit(polls):
+    """Polls of a grid-barrier wait of the persistent ensemble launch before
+    it gives up (default 4194304; 0: every wait gives up at once)."""
+    rc = lib().ppmlr_set_ensemble_barrier_limit(int(polls))
+    if rc != PPMLR_OK:
+        raise PPMLRError(rc, "bad barrier poll limit")
 
 
 def ensemble_autotune(ctxs, states, reps=1, cfl=0.4, stream=None):

@@ -45,11 +45,20 @@ def _members(k=4, seed=4):
     return [_member(N, m["sw"]) for N, m in zip(sizes, spec)]
 
 
+@pytest.fixture(params=["persistent", "per-sweep"])
+def launch(request):
+    from paper_1607_02214_amd import ppmlr
+    ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PERSISTENT if request.param == "persistent"
+                              else ppmlr.ENSEMBLE_PER_SWEEP)
+    yield request.param
+    ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PER_SWEEP)     # the library's default
+
+
 @pytest.mark.parametrize("dtype,block", [(torch.float32, 256), (torch.float32, 512), (torch.float64, 256)])
-def test_ensemble_members_equal_solo_runs_bitwise(dtype, block):
+def test_ensemble_members_equal_solo_runs_bitwise(dtype, block, launch):
     from paper_1607_02214_amd import ppmlr
     mem = _members()
-    GC.log(f"[ensemble] {len(mem)} members {[len(m.faces[0]) - 1 for m in mem]} {dtype} block {block}")
+    GC.log(f"[ensemble] {launch} {len(mem)} members {[len(m.faces[0]) - 1 for m in mem]} {dtype} block {block}")
     ctxs = [_ctx(m) for m in mem]
     us = [torch.from_numpy(m.U).to("cuda", dtype).contiguous() for m in mem]
     steps = 3
@@ -74,7 +83,7 @@ def test_ensemble_members_equal_solo_runs_bitwise(dtype, block):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_ensemble_with_segmented_members_equals_solo_runs_bitwise(dtype):
+def test_ensemble_with_segmented_members_equals_solo_runs_bitwise(dtype, launch):
     # members 0 and 2 cut their pencils into segments (on all axes, or on z
     # only), members 1 and 3 keep whole pencils; 3 steps = 9 sweeps, so the
     # alternating members end in their second state and are copied back
@@ -134,6 +143,40 @@ def test_ensemble_rejects_bad_arguments():
         ppmlr.ensemble_run(ctxs, us, 1, 0.4, block=128)
     with pytest.raises(ppmlr.PPMLRError):
         ppmlr.ensemble_run(ctxs, [us[0], us[1].double()], 1, 0.4, block=256)
+
+
+def test_persistent_barrier_gives_up_and_reports():
+    # a barrier poll limit of 0 makes every grid-barrier wait of the
+    # persistent launch give up at its first poll: the kernel leaves, and the
+    # call reports PPMLR_EDEVICE instead of hanging; a later call with the
+    # default limit runs normally and equals a solo run
+    from paper_1607_02214_amd import ppmlr
+    mem = _members(3)
+    ctxs = [_ctx(m) for m in mem]
+    us = [torch.from_numpy(m.U).to("cuda", torch.float32).contiguous() for m in mem]
+    ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PERSISTENT)
+    try:
+        ppmlr.set_ensemble_barrier_limit(0)
+        try:
+            with pytest.raises(ppmlr.PPMLRError) as ei:
+                ppmlr.ensemble_run(ctxs, us, 2, 0.4, block=256)
+            assert ei.value.status == ppmlr.PPMLR_EDEVICE and "barrier" in str(ei.value)
+        finally:
+            ppmlr.set_ensemble_barrier_limit(1 << 22)
+        ctxs = [_ctx(m) for m in mem]
+        us = [torch.from_numpy(m.U).to("cuda", torch.float32).contiguous() for m in mem]
+        assert ppmlr.ensemble_run(ctxs, us, 2, 0.4, block=256) == [0, 0, 0]
+    finally:
+        ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PER_SWEEP)
+    solo = _ctx(mem[1])
+    for ax in range(3):
+        M = len(mem[1].faces[ax]) - 1 + 14
+        nq = (len(mem[1].faces[1]) - 1) if ax == 0 else (len(mem[1].faces[0]) - 1)
+        solo.set_tile(ax, max(1, min(256 // M, nq)))
+    w = torch.from_numpy(mem[1].U).to("cuda", torch.float32).contiguous()
+    solo.advance(w, 2, 0.4)
+    torch.cuda.synchronize()
+    assert torch.equal(us[1], w)
 
 
 def test_one_failing_member_leaves_the_others_running():
