@@ -302,6 +302,28 @@ ppmlr_status ppmlr_set_ensemble_launch(int mode);
  * undefined).  EINVAL for a negative value. */
 ppmlr_status ppmlr_set_ensemble_barrier_limit(long long polls);
 
+/* ppmlr_ensemble_run without device allocation, for callers that cannot
+ * allocate device memory during the call (tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, arithmetic and results as
+ * ppmlr_ensemble_run (bitwise), but the per-call work tables (sweep
+ * descriptors, tile offsets, per-member dt pointers) live in one fixed
+ * library array in device memory instead of being allocated and freed:
+ * about 250 KB per GPU, taken when a process first calls this function on
+ * that GPU and held until the process ends.  Limits and errors:
+ *   - at most 64 members (more: PPMLR_EINVAL with a message);
+ *   - all contexts on one device (else PPMLR_EINVAL);
+ *   - a member cut into pencil segments needs its context's second state
+ *     to exist already (it is allocated by the first segmented sweep,
+ *     ppmlr_ensemble_run or ppmlr_advance of that context); otherwise
+ *     PPMLR_EINVAL, and nothing is allocated.
+ * Every call on one GPU uses the same array and overwrites the previous
+ * call's tables: calls on one stream are ordered, but calls that overlap on
+ * one GPU (other streams, other host threads) race and must not be made.
+ * Synchronises (after uploading the tables and in the per_member check).
+ * No hipMalloc, hipFree or other device-allocating routine is called. */
+ppmlr_status ppmlr_ensemble_run_noalloc(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
+                                        double cfl, int block, ppmlr_status *per_member);
+
 /* Ensemble tile autotuner: times `reps` ensemble steps for each feasible
  * workgroup size (256, 512, 1024) and target segment length (whole pencils,
  * or segments of about 96, 64, 48 or 32 interior zones) on library-owned

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1781,9 +1782,84 @@ ppmlr_status ensemble_check(ppmlr_ctx *const *ctxs, const ppmlr_state *const *st
     return PPMLR_OK;
 }
 
+// Most members of one ppmlr_ensemble_run_noalloc call, and the bytes of its
+// work tables at that count (FP64 descriptors are the larger).
+constexpr int kNoallocMaxMembers = 64;
+constexpr size_t kNoallocBytes = EnsTables<double>::bytes(kNoallocMaxMembers);
+static_assert(EnsTables<float>::bytes(kNoallocMaxMembers) <= kNoallocBytes, "FP32 tables fit");
+
+}  // namespace
+
+// Work tables of ppmlr_ensemble_run_noalloc: a fixed array in device memory,
+// one copy per GPU that the library runs on, held until the process ends.
+// Host code never uses this name as a device address: each device's address
+// comes from hipGetSymbolAddress (noalloc_tables below).
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on device dev, looked up once per device with that
+// device current (and the caller's current device restored).
+ppmlr_status noalloc_tables(ppmlr_ctx *c, int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, PPMLR_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        ppmlr_status e = hip_check(c, hipGetDevice(&cur), "hipGetDevice");
+        if (!e && cur != dev) e = hip_check(c, hipSetDevice(dev), "hipSetDevice");
+        if (e) return e;
+        void *ptr = nullptr;
+        e = hip_check(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (cur != dev) {
+            ppmlr_status e2 = hip_check(c, hipSetDevice(cur), "hipSetDevice");
+            if (!e) e = e2;
+        }
+        if (e) return e;
+        if (!ptr) return fail(c, PPMLR_EDEVICE, "hipGetSymbolAddress returned no address");
+        g_scratch_ptr[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PPMLR_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ppmlr_status ppmlr_ensemble_run_noalloc(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
+                                        double cfl, int block, ppmlr_status *per_member)
+{
+    if (block == 0) block = g_ensemble_block ? g_ensemble_block : 512;
+    ppmlr_status e = ensemble_check(ctxs, states, n, steps, cfl, block);
+    if (e) return e;
+    if (n > kNoallocMaxMembers)
+        return fail(ctxs[0], PPMLR_EINVAL, "ppmlr_ensemble_run_noalloc takes at most " +
+                                               std::to_string(kNoallocMaxMembers) + " members, got " +
+                                               std::to_string(n));
+    for (int m = 1; m < n; ++m)
+        if (ctxs[m]->device != ctxs[0]->device)
+            return fail(ctxs[0], PPMLR_EINVAL, "members are on different devices");
+    if (steps > 0) {
+        unsigned char *tables = nullptr;
+        e = noalloc_tables(ctxs[0], ctxs[0]->device, &tables);
+        if (!e)
+            e = states[0]->dtype == PPMLR_F64
+                    ? ensemble_typed<double>(ctxs, states, n, steps, cfl, block, tables,
+                                             g_ensemble_launch == PPMLR_ENSEMBLE_PERSISTENT)
+                    : ensemble_typed<float>(ctxs, states, n, steps, cfl, block, tables,
+                                            g_ensemble_launch == PPMLR_ENSEMBLE_PERSISTENT);
+        if (!e)
+            for (int m = 0; m < n; ++m) ctxs[m]->step += steps;
+    }
+    if (per_member)
+        for (int m = 0; m < n; ++m) per_member[m] = e ? e : ppmlr_status_check(ctxs[m], states[m]->stream);
+    return e;
+}
 
 ppmlr_status ppmlr_ensemble_run(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int steps,
                                 double cfl, int block, ppmlr_status *per_member)

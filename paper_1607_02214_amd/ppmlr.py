@@ -127,6 +127,8 @@ SIGNATURES = {
     "ppmlr_autotune": (C.c_int, [_P, C.POINTER(State), C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_ensemble_run": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
                                      C.c_int, C.POINTER(C.c_int)]),
+    "ppmlr_ensemble_run_noalloc": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int,
+                                             C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "ppmlr_set_ensemble_launch": (C.c_int, [C.c_int]),
     "ppmlr_set_ensemble_barrier_limit": (C.c_int, [C.c_longlong]),
     "ppmlr_ensemble_autotune": (C.c_int, [C.POINTER(_P), C.POINTER(C.POINTER(State)), C.c_int, C.c_int, C.c_double,
@@ -392,14 +394,16 @@ def _ensemble_args(ctxs, states, stream):
     return n, hs, sts, sp
 
 
-def ensemble_run(ctxs, states, steps, cfl, block=0, stream=None):
+def ensemble_run(ctxs, states, steps, cfl, block=0, stream=None, noalloc=False):
     """Advance every member (context, state tensor) by `steps` split steps,
     all members in each launch (one launch per sweep, or one per call in the
     persistent form, see set_ensemble_launch); returns the per-member status
-    codes."""
+    codes.  noalloc: call ppmlr_ensemble_run_noalloc (work tables in the
+    library's fixed device array; at most 64 members)."""
     n, hs, sts, sp = _ensemble_args(ctxs, states, stream)
     per = (C.c_int * n)()
-    rc = lib().ppmlr_ensemble_run(hs, sp, n, int(steps), float(cfl), int(block), per)
+    fn = lib().ppmlr_ensemble_run_noalloc if noalloc else lib().ppmlr_ensemble_run
+    rc = fn(hs, sp, n, int(steps), float(cfl), int(block), per)
     if rc != PPMLR_OK:
         msg = lib().ppmlr_last_error(ctxs[0].h)
         raise PPMLRError(rc, msg.decode() if msg else "")
