@@ -53,6 +53,8 @@ class Problem(C.Structure):
         ("r_inner", C.c_double),
         ("inner_rho", C.c_double),
         ("inner_p", C.c_double),
+        ("inner_v", C.POINTER(C.c_double)),
+        ("inner_box", C.c_int * 6),
         ("flatten", C.c_int),
         ("janhunen", C.c_int),
         ("max_iter", C.c_int),
@@ -178,6 +180,25 @@ class OracleProblem:
     @property
     def shape(self):
         return (8, self.p.n[2], self.p.n[1], self.p.n[0])
+
+    def set_inner_velocity(self, box=None, v=None):
+        """Velocity of the zones the inner boundary resets (the ionosphere's
+        drift): box = (i0, i1, j0, j1, k0, k1) zone-index ranges (half-open),
+        v: [3, k1 - k0, j1 - j0, i1 - i0].  None: the reset zones are at rest."""
+        if v is None:
+            self._inner_v = None
+            self.p.inner_v = None
+            for q in range(6):
+                self.p.inner_box[q] = 0
+            return
+        i0, i1, j0, j1, k0, k1 = (int(b) for b in box)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        if v.shape != (3, k1 - k0, j1 - j0, i1 - i0):
+            raise ValueError("velocity box shape does not match the box")
+        self._inner_v = v
+        self.p.inner_v = _dptr(v)
+        for q, b in enumerate((i0, i1, j0, j1, k0, k1)):
+            self.p.inner_box[q] = b
 
     def sweep(self, U: np.ndarray, dt: float, axis: int, stats: Stats | None = None) -> np.ndarray:
         U = np.ascontiguousarray(U, dtype=np.float64).copy()

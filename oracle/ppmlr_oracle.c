@@ -76,6 +76,12 @@ typedef struct {
     double inflow[8];         /* rho, vx, vy, vz, Bx, By, Bz (total field), p */
     double r_inner;           /* zones with centre radius < r_inner are reset */
     double inner_rho, inner_p;
+    const double *inner_v;    /* optional velocity of the reset zones (the
+                                 ionosphere's E x B drift): [3][box] over the
+                                 index box inner_box = (i0, i1, j0, j1, k0, k1),
+                                 x fastest; NULL (or a zone outside the box):
+                                 at rest */
+    int inner_box[6];
     int flatten;              /* CW84 appendix shock flattening on/off */
     int janhunen;             /* -v div B' induction source on/off */
     int max_iter;
@@ -492,7 +498,7 @@ typedef struct {
  *   (xf[i] is the left face of zone i), c1, c2: the pencil's transverse
  *   centre coordinates (axes t1, t2).
  * Output: Uout[8][N] interior zones. */
-static void sweep_pencil(const oracle_problem *pr, int axis, int N,
+static void sweep_pencil(const oracle_problem *pr, int axis, int N, int j1, int j2,
                          double *const U[NV], const double *dx, const double *xc,
                          const double *xf, double c1, double c2, double dt,
                          double *const Uout[NV], oracle_stats *st, double *face_states)
@@ -804,10 +810,27 @@ static void sweep_pencil(const oracle_problem *pr, int axis, int N,
             pos[n] = xc[i]; pos[t1] = c1; pos[t2] = c2;
             double r = sqrt(pos[0] * pos[0] + pos[1] * pos[1] + pos[2] * pos[2]);
             if (r < pr->r_inner) {
+                /* the inner state: rest, or the velocity the ionosphere
+                 * coupling set for this zone */
+                double v[3] = {0.0, 0.0, 0.0};
+                if (pr->inner_v) {
+                    int ijk[3];
+                    ijk[n] = i - NG; ijk[t1] = j1; ijk[t2] = j2;
+                    const int *bx = pr->inner_box;
+                    if (ijk[0] >= bx[0] && ijk[0] < bx[1] && ijk[1] >= bx[2] && ijk[1] < bx[3] &&
+                        ijk[2] >= bx[4] && ijk[2] < bx[5]) {
+                        size_t nb = (size_t)(bx[1] - bx[0]) * (bx[3] - bx[2]) * (bx[5] - bx[4]);
+                        size_t o = ((size_t)(ijk[2] - bx[4]) * (bx[3] - bx[2]) + (ijk[1] - bx[2])) *
+                                       (bx[1] - bx[0]) + (ijk[0] - bx[0]);
+                        for (int k = 0; k < 3; ++k) v[k] = pr->inner_v[k * nb + o];
+                    }
+                }
                 out[0] = pr->inner_rho;
-                out[1] = out[2] = out[3] = 0.0;
+                out[1] = pr->inner_rho * v[0];
+                out[2] = pr->inner_rho * v[1];
+                out[3] = pr->inner_rho * v[2];
                 out[4] = out[5] = out[6] = 0.0;
-                out[7] = pr->inner_p / (g - 1.0);
+                out[7] = pr->inner_p / (g - 1.0) + 0.5 * pr->inner_rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
             }
         }
         for (int v = 0; v < NV; ++v) Uout[v][i - NG] = out[v];
@@ -954,7 +977,7 @@ int oracle_sweep(const oracle_problem *pr, double *U3, double dt, int axis, orac
         for (int pidx = 0; pidx < npen; ++pidx) {
             int j1 = pidx % pr->n[t1], j2 = pidx / pr->n[t1];
             extract_pencil(pr, src, a, j1, j2, xc, xc1[j1], xc2[j2], P);
-            sweep_pencil(pr, a, N, P, dx, xc, xf, xc1[j1], xc2[j2], dt, O, &loc, NULL);
+            sweep_pencil(pr, a, N, j1, j2, P, dx, xc, xf, xc1[j1], xc2[j2], dt, O, &loc, NULL);
             for (int s = 0; s < N; ++s) {
                 int ijk[3];
                 pencil_ijk(a, s, j1, j2, ijk);
@@ -1015,7 +1038,7 @@ int oracle_sweep_pencils(const oracle_problem *pr, const double *U3, double dt, 
             double c2 = 0.5 * (pr->faces[t2][j2] + pr->faces[t2][j2 + 1]);
             for (int v = 0; v < NV; ++v) O[v] = out + ((size_t)p * NV + v) * N;
             extract_pencil(pr, U3, a, j1, j2, xc, c1, c2, P);
-            sweep_pencil(pr, a, N, P, dx, xc, xf, c1, c2, dt, O, &loc, NULL);
+            sweep_pencil(pr, a, N, j1, j2, P, dx, xc, xf, c1, c2, dt, O, &loc, NULL);
         }
 #pragma omp critical
         {
@@ -1060,7 +1083,7 @@ int oracle_face_states(const oracle_problem *pr, const double *U3, double dt, in
     oracle_stats loc;
     memset(&loc, 0, sizeof(loc));
     extract_pencil(pr, U3, a, j1, j2, xc, c1, c2, P);
-    sweep_pencil(pr, a, N, P, dx, xc, xf, c1, c2, dt, O, &loc, out);
+    sweep_pencil(pr, a, N, j1, j2, P, dx, xc, xf, c1, c2, dt, O, &loc, out);
     free(dx); free(xc); free(xf); free(pbuf); free(obuf);
     return 0;
 }
