@@ -44,13 +44,14 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources with comments and whitespace removed (a
-    comment edit does not make the committed counters stale; any code edit
-    does)."""
+    """Hash of the sweep kernel's HIP sources (the sweep body and the headers
+    it includes) with comments and whitespace removed: a comment edit does
+    not make the committed counters of the sweep stale, any code edit does.
+    The tile shape the counters were taken with is recorded beside them."""
     import re
     h = hashlib.sha256()
     for rel in ("paper_1607_02214_amd/csrc/ppmlr_sweep.hpp", "paper_1607_02214_amd/csrc/ppmlr_mlp.hpp",
-                "paper_1607_02214_amd/csrc/ppmlr_lib.hip"):
+                "paper_1607_02214_amd/csrc/ppmlr_char.hpp"):
         with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
             src = f.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
@@ -168,6 +169,54 @@ def series_leg(args, setup, make_ctx, shape_ctx):
             "ms_per_step": ms / args.steps, "knots": len(times), "series_span": [0.0, float(t_end)],
             "simulated_time": ctx.time(u), "status": ctx.status_check(),
             "finite": bool(torch.isfinite(u).all().item())}
+
+
+def ionosphere_leg(args, setup, make_ctx, shape_ctx, u_dev):
+    """The ionosphere shell coupling on the headline run's developed flow
+    (the plain run's final FP32 state, copied): one coupling timed alone
+    (shell current, potential, drift of the reset zones: three kernels and
+    a synchronisation), then args.steps steps with a coupling before each,
+    the plain run's tile shape."""
+    import numpy as np
+    import torch
+    from paper_1607_02214_amd import ppmlr
+
+    ctx = make_ctx()
+    for a in range(3):
+        ctx.set_tile(a, 1)
+        ctx.set_segments(a, shape_ctx.get_segments(a))
+        ctx.set_tile(a, shape_ctx.get_tile(a))
+        ctx.set_segment_order(a, shape_ctx.get_segment_order(a))
+    u = u_dev.clone()
+    prm = ppmlr.iono_default_params()
+    shape = (2, prm.n_theta, prm.n_phi)
+    jr = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    phi = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    ctx.ionosphere_couple(u, prm, jr=jr, phi=phi)          # buffers, first use
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.ionosphere_couple(u, prm, jr=jr, phi=phi)
+    ms_couple = (time.perf_counter() - t0) * 1000.0 / reps   # host-timed: each call synchronises
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        ctx.ionosphere_couple(u, prm)
+        ctx.advance(u, 1, args.cfl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    zones = int(np.prod(setup.U.shape[1:]))
+    # 1 kV in code units: v_0 B_0 R_E = 21.81 km/s * 1 nT * 6371 km
+    kv = 21.81e3 * 1e-9 * 6.371e6 / 1e3
+    return {"value": zones * args.steps / (ms / 1000.0), "unit": "zone-updates/s", "steps": args.steps,
+            "ms_per_step": ms / args.steps, "ms_per_coupling": round(ms_couple, 4),
+            "shell_cells": [2, prm.n_theta, prm.n_phi],
+            "r_shell": prm.r_shell, "r_fac": prm.r_fac, "sigma_code": prm.sigma,
+            "max_abs_jr": float(jr.abs().max().item()),
+            "cross_polar_cap_potential_kV": [float((phi[h].max() - phi[h].min()).item()) * kv for h in range(2)],
+            "status": ctx.status_check(), "finite": bool(torch.isfinite(u).all().item())}
 
 
 def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain, ref64=None):
@@ -467,6 +516,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-series", action="store_true")
+    ap.add_argument("--no-iono", action="store_true", help="skip the ionosphere coupling leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 512x384x384 leg")
     ap.add_argument("--c3-steps", type=int, default=20)
     ap.add_argument("--harvest-steps", type=int, default=105,
@@ -675,6 +725,10 @@ def main():
         print("[bench] inflow time series", file=sys.stderr, flush=True)
         out["inflow_series"] = series_leg(args, setup, make_ctx, ctx)
         torch.cuda.empty_cache()
+    if not args.no_iono:
+        print("[bench] ionosphere coupling", file=sys.stderr, flush=True)
+        out["ionosphere"] = ionosphere_leg(args, setup, make_ctx, ctx, u)
+        torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned"] = learned_leg(args, setup, make_ctx, u, st, value,
                                      ref64=None if args.no_fp64 else (ctx_r, u_r))
@@ -692,9 +746,13 @@ def main():
         avg64 = [kms64[a] / kn64[a] if kn64[a] else 0.0 for a in range(3)]
         d64 = int(np.argmax(avg64))
         ach64 = 128.0 * zones / (avg64[d64] / 1000.0) / 1e9
+        traffic64, _ = load_traffic("f64")
         out["fp64_plain"] = {"value": v64, "steps": n64, "ms_per_step": ms64 / n64,
-                             "roofline_frac": round(ach64 / HBM_PEAK_GBS, 4), "status": status64,
-                             "finite": fin64, "fp32_speedup": value / v64}
+                             "roofline_frac": round(ach64 / HBM_PEAK_GBS, 4),
+                             "dominant_kernel": f"sweep axis {'xyz'[d64]} (f64)",
+                             "avg_launch_ms": [round(a, 4) for a in avg64],
+                             "traffic": traffic64["bytes_per_launch"][str(d64)] if traffic64 else None,
+                             "status": status64, "finite": fin64, "fp32_speedup": value / v64}
         del u64
         torch.cuda.empty_cache()
 

@@ -163,8 +163,66 @@ ppmlr_status ppmlr_set_inflow(ppmlr_ctx *ctx, const double prim[8]);
  * Ensembles do not take series.  Synchronises the device. */
 ppmlr_status ppmlr_set_inflow_series(ppmlr_ctx *ctx, int n, const double *t, const double *prim);
 
-/* State the zones inside r_inner are reset to (rest, B' = 0). */
+/* State the zones inside r_inner are reset to (rest, B' = 0; with an
+ * ionosphere coupling attached, the drift it set, see below). */
 ppmlr_status ppmlr_set_inner(ppmlr_ctx *ctx, double rho, double p);
+
+/* ------------------------------------------------------------------ */
+/* Ionosphere shell coupling (Section II: a thin shell at 1.017 R_E     */
+/* closes the field-aligned currents; the electrostatic potential        */
+/* solved on it is carried along dipole field lines to the inner         */
+/* boundary, where it sets the flow)                                     */
+/* ------------------------------------------------------------------ */
+
+/* Shell parameters.  ppmlr_iono_default_params() fills the defaults noted. */
+typedef struct {
+    int n_theta;        /* cells per polar cap in magnetic colatitude, 32 */
+    int n_phi;          /* cells in longitude, 64; n_theta * n_phi <= 4096
+                           and 8 * (4 n_theta n_phi + 3 n_theta + 2 n_phi)
+                           bytes must fit the 160 KiB of LDS */
+    double r_shell;     /* shell radius, 1.017 (R_E) */
+    double r_fac;       /* radius where the field-aligned current is taken
+                           on each cell's field line, 3.5 (> r_shell; the
+                           sphere, with one zone of margin for the central
+                           differences, must lie inside the grid) */
+    double sigma;       /* height-integrated Pedersen conductance in code
+                           units (mu_0 = 1: S times mu_0 v_0), 5 S = 0.137 */
+} ppmlr_iono_params;
+
+void ppmlr_iono_default_params(ppmlr_iono_params *p);
+
+/* One coupling of the state (FP32 or FP64, on its stream):
+ *   1. j_r: the radial current density reaching each shell cell, from
+ *      J = curl B' at the zone centres (central differences) around the point
+ *      where the cell's dipole field line crosses r_fac (trilinear
+ *      interpolation), its component along the dipole, times
+ *      |B(shell)| / |B(r_fac)| (J_par / |B| is constant along a flux tube);
+ *   2. Phi: div_h(sigma grad_h Phi) = j_r on the polar cap of each hemisphere
+ *      whose field lines cross r_fac (magnetic colatitude theta with
+ *      sin^2 theta <= r_shell / r_fac), Phi = 0 at its edge; finite volumes
+ *      on cells uniform in theta and longitude, solved directly in FP64 (a
+ *      discrete Fourier transform in longitude, one tridiagonal system per
+ *      mode in colatitude: the conductance is uniform);
+ *   3. the drift v = E x B_d / |B_d|^2 of every zone with centre inside
+ *      r_inner, E = -grad Phi by central differences of the potential at the
+ *      footpoints of the zone's and its neighbours' field lines (zero where a
+ *      zone or neighbour lies inside the shell), kept by the context: every
+ *      later sweep resets those zones to (inner rho, v, inner p, B' = 0)
+ *      until ppmlr_ionosphere_detach.
+ * Magnetic frame: z_m opposite to the dipole moment, x_m the x axis
+ * projected off z_m; hemisphere 0 is z_m > 0; cell (h, k, j) at colatitude
+ * (k + 1/2) theta_c / n_theta and longitude (j + 1/2) 2 pi / n_phi.
+ * jr, phi (device pointers, may be NULL) receive [2][n_theta][n_phi] FP64.
+ * EINVAL without a
+ * dipole or an inner boundary, for bad parameters, or when the sphere r_fac
+ * does not fit inside the zone centres with one zone of margin.  The
+ * context allocates its work buffers at the first call (and again when the
+ * shell grows).  Synchronises. */
+ppmlr_status ppmlr_ionosphere_couple(ppmlr_ctx *ctx, const ppmlr_state *state, const ppmlr_iono_params *params,
+                                     double *jr, double *phi);
+
+/* Back to the inner state at rest. */
+ppmlr_status ppmlr_ionosphere_detach(ppmlr_ctx *ctx);
 
 /* One 1D sweep along axis (0 = x, 1 = y, 2 = z) over every pencil of the
  * grid (Section III-A: the 3D equations split into independent 1D
@@ -330,7 +388,9 @@ ppmlr_status ppmlr_ensemble_run_noalloc(ppmlr_ctx *const *ctxs, const ppmlr_stat
  * copies of the states (the callers' states, step counters and times are
  * left unchanged), stores the fastest workgroup size for ensemble calls with
  * block = 0, returns it in *block (may be NULL), and sets every member
- * context's segments per axis to the fastest length's. */
+ * context's segments per axis to the fastest length's; then, at that
+ * workgroup size, tries each other length for one axis at a time (over at
+ * least 5 steps) and keeps it where it is faster. */
 ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *const *states, int n, int reps,
                                      double cfl, int *block);
 

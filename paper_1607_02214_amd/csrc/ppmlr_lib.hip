@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "ppmlr.h"
+#include "ppmlr_iono.hpp"
 #include "ppmlr_sweep.hpp"
 
 using ppmlr::kG;
@@ -71,6 +72,14 @@ struct ppmlr_ctx {
     float *harvest = nullptr;                // caller-owned interface records
     long long harvest_cap = 0;
     unsigned long long *harvest_count = nullptr;
+    // ionosphere coupling: shell buffers (j_r, Phi, pole values) and the
+    // drift of the reset zones over an index box
+    double *d_iono = nullptr;
+    size_t iono_bytes = 0;
+    double *d_inner_v = nullptr;
+    size_t inner_v_bytes = 0;
+    int inner_box[6] = {0, 0, 0, 0, 0, 0};
+    bool inner_drift = false;
 };
 
 struct ppmlr_mlp {
@@ -311,6 +320,10 @@ void fill_args(const ppmlr_ctx *c, ppmlr::SweepArgs<T> &a, const T *in, T *u, in
     a.r_inner2 = (T)(c->r_inner * c->r_inner);
     a.inner_rho = (T)c->inner_rho;
     a.inner_E = (T)(c->inner_p / (c->gamma - 1.0));
+    if (c->inner_drift) {
+        a.inner_v = c->d_inner_v;
+        for (int q = 0; q < 6; ++q) a.ib[q] = c->inner_box[q];
+    }
     a.flatten = c->opt.flatten;
     a.janhunen = c->opt.janhunen;
     a.max_iter = c->opt.max_iter;
@@ -883,6 +896,8 @@ void ppmlr_destroy(ppmlr_ctx *c)
     if (c->d_mlp_theta) (void)hipFree(c->d_mlp_theta);
     if (c->d_series) (void)hipFree(c->d_series);
     if (c->d_inflow) (void)hipFree(c->d_inflow);
+    if (c->d_iono) (void)hipFree(c->d_iono);
+    if (c->d_inner_v) (void)hipFree(c->d_inner_v);
     free_tables(c);
     delete c;
 }
@@ -957,6 +972,152 @@ ppmlr_status ppmlr_set_inner(ppmlr_ctx *c, double rho, double p)
         return fail(c, PPMLR_EINVAL, "inner state needs rho > 0, p > 0");
     c->inner_rho = rho;
     c->inner_p = p;
+    return PPMLR_OK;
+}
+
+void ppmlr_iono_default_params(ppmlr_iono_params *p)
+{
+    if (!p) return;
+    p->n_theta = 32;
+    p->n_phi = 64;
+    p->r_shell = 1.017;
+    p->r_fac = 3.5;
+    p->sigma = 5.0 * 4.0e-7 * M_PI * 21.81e3;   // 5 S in code units (mu_0 v_0 per siemens)
+}
+
+ppmlr_status ppmlr_ionosphere_detach(ppmlr_ctx *c)
+{
+    if (!c) return PPMLR_EINVAL;
+    c->inner_drift = false;
+    return PPMLR_OK;
+}
+
+ppmlr_status ppmlr_ionosphere_couple(ppmlr_ctx *c, const ppmlr_state *s, const ppmlr_iono_params *prm, double *jr,
+                                     double *phi)
+{
+    ppmlr_status e = check_state(c, s);
+    if (e) return e;
+    if (!prm) return fail(c, PPMLR_EINVAL, "null parameters");
+    if (c->dip_m == 0.0) return fail(c, PPMLR_EINVAL, "the ionosphere coupling needs a dipole");
+    if (!(c->r_inner > 0.0)) return fail(c, PPMLR_EINVAL, "the ionosphere coupling needs an inner boundary");
+    const int nt = prm->n_theta, nph = prm->n_phi;
+    if (nt < 2 || nph < 4 || (long long)nt * nph > ppmlr::kIonoMaxCells)
+        return fail(c, PPMLR_EINVAL, "shell cells: n_theta >= 2, n_phi >= 4, n_theta * n_phi <= 4096");
+    const long long N = (long long)nt * nph;
+    const size_t lds = sizeof(double) * (size_t)(4 * N + 3 * nt + 2 * nph);
+    if (lds > 160 * 1024) return fail(c, PPMLR_EINVAL, "shell arrays do not fit the LDS");
+    if (!(prm->r_fac > prm->r_shell) || !(prm->r_shell > 0.0) || !(prm->sigma > 0.0) ||
+        !std::isfinite(prm->r_fac) || !std::isfinite(prm->sigma))
+        return fail(c, PPMLR_EINVAL, "shell parameters: r_fac > r_shell > 0, sigma > 0");
+    // the sphere r_fac with the central differences' neighbours inside the grid
+    for (int a = 0; a < 3; ++a) {
+        const std::vector<double> &f = c->faces[a];
+        const int n = c->n[a];
+        if (n < 4) return fail(c, PPMLR_EINVAL, "the ionosphere coupling needs 4 or more zones per axis");
+        const double c1 = 0.5 * (f[1] + f[2]), cn2 = 0.5 * (f[n - 2] + f[n - 1]);
+        if (!(c1 < -prm->r_fac) || !(prm->r_fac < cn2))
+            return fail(c, PPMLR_EINVAL, "the sphere r_fac does not fit inside the zone centres");
+    }
+    hipStream_t st = (hipStream_t)s->stream;
+    // magnetic frame: z_m opposite to the dipole moment
+    double m[3] = {c->dir[0], c->dir[1], c->dir[2]};
+    const double mn = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    ppmlr::IonoArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int d = 0; d < 3; ++d) {
+        a.mdir[d] = m[d] / mn;
+        a.zm[d] = -a.mdir[d];
+    }
+    {
+        double x[3] = {1.0, 0.0, 0.0};
+        double dz = a.zm[0];
+        double xm[3] = {x[0] - dz * a.zm[0], x[1] - dz * a.zm[1], x[2] - dz * a.zm[2]};
+        double nx_ = std::sqrt(xm[0] * xm[0] + xm[1] * xm[1] + xm[2] * xm[2]);
+        if (nx_ < 1e-6) {
+            double y[3] = {0.0, 1.0, 0.0};
+            dz = a.zm[1];
+            for (int d = 0; d < 3; ++d) xm[d] = y[d] - dz * a.zm[d];
+            nx_ = std::sqrt(xm[0] * xm[0] + xm[1] * xm[1] + xm[2] * xm[2]);
+        }
+        for (int d = 0; d < 3; ++d) a.xm[d] = xm[d] / nx_;
+        a.ym[0] = a.zm[1] * a.xm[2] - a.zm[2] * a.xm[1];
+        a.ym[1] = a.zm[2] * a.xm[0] - a.zm[0] * a.xm[2];
+        a.ym[2] = a.zm[0] * a.xm[1] - a.zm[1] * a.xm[0];
+    }
+    a.u = s->u;
+    a.nx = c->n[0]; a.ny = c->n[1]; a.nz = c->n[2];
+    a.vol = (long long)a.nx * a.ny * a.nz;
+    a.xc = c->tab[0].xci64; a.yc = c->tab[1].xci64; a.zc = c->tab[2].xci64;
+    a.M = c->dip_m;
+    a.nt = nt; a.nph = nph;
+    a.r_shell = prm->r_shell; a.r_fac = prm->r_fac;
+    a.theta_c = std::asin(std::sqrt(prm->r_shell / prm->r_fac));
+    a.dth = a.theta_c / nt;
+    a.dph = 2.0 * M_PI / nph;
+    a.sigma = prm->sigma;
+    a.r_inner2 = c->r_inner * c->r_inner;
+    // index box of the zones inside r_inner
+    bool have_box = true;
+    for (int d = 0; d < 3; ++d) {
+        const std::vector<double> &f = c->faces[d];
+        int lo = -1, hi = -1;
+        for (int i = 0; i < c->n[d]; ++i) {
+            const double x = 0.5 * (f[i] + f[i + 1]);
+            if (x * x < a.r_inner2) { if (lo < 0) lo = i; hi = i + 1; }
+        }
+        if (lo < 0) { have_box = false; break; }
+        a.box[2 * d] = lo;
+        a.box[2 * d + 1] = hi;
+    }
+    const long long nb = have_box ? (long long)(a.box[1] - a.box[0]) * (a.box[3] - a.box[2]) * (a.box[5] - a.box[4]) : 0;
+    // work buffers
+    const size_t need = sizeof(double) * (size_t)(4 * N + 2);
+    if (c->iono_bytes < need) {
+        if (c->d_iono) { (void)hipStreamSynchronize(st); (void)hipFree(c->d_iono); c->d_iono = nullptr; c->iono_bytes = 0; }
+        e = hip_check(c, hipMalloc((void **)&c->d_iono, need), "hipMalloc");
+        if (e) return e;
+        c->iono_bytes = need;
+    }
+    const size_t vneed = sizeof(double) * (size_t)std::max<long long>(3 * nb, 1);
+    if (c->inner_v_bytes < vneed) {
+        c->inner_drift = false;
+        if (c->d_inner_v) { (void)hipStreamSynchronize(st); (void)hipFree(c->d_inner_v); c->d_inner_v = nullptr; c->inner_v_bytes = 0; }
+        e = hip_check(c, hipMalloc((void **)&c->d_inner_v, vneed), "hipMalloc");
+        if (e) return e;
+        c->inner_v_bytes = vneed;
+    }
+    a.jr = c->d_iono;
+    a.phi = c->d_iono + 2 * N;
+    a.pole = c->d_iono + 4 * N;
+    a.v = c->d_inner_v;
+    const unsigned fac_blocks = (unsigned)((2 * N + 255) / 256);
+    if (s->dtype == PPMLR_F64)
+        hipLaunchKernelGGL(ppmlr::iono_fac_kernel<double>, dim3(fac_blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(ppmlr::iono_fac_kernel<float>, dim3(fac_blocks), dim3(256), 0, st, a);
+    e = hip_check(c, hipGetLastError(), "ionosphere current launch");
+    if (e) return e;
+    if (lds > 64 * 1024) {
+        e = hip_check(c, hipFuncSetAttribute((const void *)ppmlr::iono_solve_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                      "hipFuncSetAttribute");
+        if (e) return e;
+    }
+    hipLaunchKernelGGL(ppmlr::iono_solve_kernel, dim3(2), dim3(ppmlr::kIonoThreads), lds, st, a);
+    e = hip_check(c, hipGetLastError(), "ionosphere potential launch");
+    if (e) return e;
+    if (nb > 0) {
+        hipLaunchKernelGGL(ppmlr::iono_drift_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, a);
+        e = hip_check(c, hipGetLastError(), "ionosphere drift launch");
+        if (e) return e;
+    }
+    if (jr) e = hip_check(c, hipMemcpyAsync(jr, a.jr, sizeof(double) * 2 * N, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    if (!e && phi)
+        e = hip_check(c, hipMemcpyAsync(phi, a.phi, sizeof(double) * 2 * N, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    if (!e) e = hip_check(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (e) return e;
+    for (int q = 0; q < 6; ++q) c->inner_box[q] = a.box[q];
+    c->inner_drift = nb > 0;
     return PPMLR_OK;
 }
 
@@ -1955,6 +2116,44 @@ ppmlr_status ppmlr_ensemble_autotune(ppmlr_ctx *const *ctxs, const ppmlr_state *
         for (int m = 0; m < n; ++m) ctxs[m]->step = step0[m];
     }
     set_lengths(best_len);
+    // then each axis's segment length on its own, at the chosen block size
+    // (the axes favour different lengths: x longer, y and z shorter), timed
+    // over at least 5 steps
+    if (!e && best) {
+        auto set_axis = [&](int ax, int len) {
+            for (int m = 0; m < n; ++m) {
+                const int N = ctxs[m]->n[ax];
+                int k = len > 0 ? (N + len - 1) / len : 0;
+                while (k > 1 && (seg_len(N, k) == 0 || seg_len(N, k) < kG)) --k;
+                ctxs[m]->seg[ax] = k;
+            }
+        };
+        const int rr = std::max(reps, 5);
+        auto timed = [&](float &ms) -> ppmlr_status {
+            ppmlr_status er = hip_check(ctxs[0], hipEventRecord(t0, st), "hipEventRecord");
+            if (!er) er = ppmlr_ensemble_run(ctxs, tptr.data(), n, rr, cfl, best, nullptr);
+            if (!er) er = hip_check(ctxs[0], hipEventRecord(t1, st), "hipEventRecord");
+            if (!er) er = hip_check(ctxs[0], hipEventSynchronize(t1), "hipEventSynchronize");
+            if (!er) er = hip_check(ctxs[0], hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+            for (int m = 0; m < n; ++m) ctxs[m]->step = step0[m];
+            return er;
+        };
+        float base_ms = 0.0f;
+        e = timed(base_ms);
+        for (int ax = 0; ax < 3 && !e; ++ax) {
+            int keep = best_len;
+            for (int q = 0; q < 5 && !e; ++q) {
+                if (lens[q] == keep) continue;
+                set_axis(ax, lens[q]);
+                float ms = 0.0f;
+                if (ensemble_check(ctxs, tptr.data(), n, rr, cfl, best) == PPMLR_OK) {
+                    e = timed(ms);
+                    if (!e && ms < base_ms) { base_ms = ms; keep = lens[q]; }
+                }
+                set_axis(ax, keep);
+            }
+        }
+    }
     for (int m = 0; m < n; ++m) {
         ctxs[m]->step = step0[m];
         ctxs[m]->opt.collect_stats = stat0[m];

@@ -156,6 +156,8 @@ struct SweepArgs {
     const double *in_dev;       // inflow of this step on the device (time series) or nullptr
     T r_inner2, inner_rho, inner_E;
     int has_inner;
+    const double *inner_v;      // drift of the reset zones [3][box] (ionosphere coupling) or nullptr: at rest
+    int ib[6];                  // its index box i0, i1, j0, j1, k0, k1 (half-open)
     int flatten, janhunen, max_iter;
     T tol, p_floor;
     unsigned long long *stats;  // kStatSlots x kStatWords counters or nullptr
@@ -1096,10 +1098,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, const int tq, 
             to_xyz<AX>(xci, c1, c2, x, y, z);
             if (x * x + y * y + z * z < a.r_inner2) {
                 masked = true;
+                // the inner state: rest, or the drift the ionosphere coupling set
+                T vx = T(0), vy = T(0), vz = T(0);
+                if (a.inner_v) {
+                    int ix, iy, iz;
+                    if (AX == 0) { ix = g; iy = j1; iz = j2; }
+                    else if (AX == 1) { iy = g; iz = j1; ix = j2; }
+                    else { iz = g; ix = j1; iy = j2; }
+                    if (ix >= a.ib[0] && ix < a.ib[1] && iy >= a.ib[2] && iy < a.ib[3] && iz >= a.ib[4] &&
+                        iz < a.ib[5]) {
+                        const long long bi = a.ib[1] - a.ib[0], bj = a.ib[3] - a.ib[2];
+                        const long long nb = bi * bj * (a.ib[5] - a.ib[4]);
+                        const long long o = ((long long)(iz - a.ib[4]) * bj + (iy - a.ib[2])) * bi + (ix - a.ib[0]);
+                        vx = (T)a.inner_v[o];
+                        vy = (T)a.inner_v[nb + o];
+                        vz = (T)a.inner_v[2 * nb + o];
+                    }
+                }
                 out[0] = a.inner_rho;
-                out[1] = out[2] = out[3] = T(0);
+                out[1] = a.inner_rho * vx;
+                out[2] = a.inner_rho * vy;
+                out[3] = a.inner_rho * vz;
                 out[4] = out[5] = out[6] = T(0);
-                out[7] = a.inner_E;
+                out[7] = a.inner_E + T(0.5) * a.inner_rho * (vx * vx + vy * vy + vz * vz);
             }
         }
         const unsigned int o = base + (unsigned int)(g * (int)a.stride_n);

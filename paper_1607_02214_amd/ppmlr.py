@@ -68,6 +68,16 @@ class Grid(C.Structure):
     ]
 
 
+class IonoParams(C.Structure):
+    _fields_ = [
+        ("n_theta", C.c_int),
+        ("n_phi", C.c_int),
+        ("r_shell", C.c_double),
+        ("r_fac", C.c_double),
+        ("sigma", C.c_double),
+    ]
+
+
 class Coords(C.Structure):
     _fields_ = [("faces", C.POINTER(C.c_double) * 3)]
 
@@ -104,6 +114,9 @@ SIGNATURES = {
     "ppmlr_set_background": (C.c_int, [_P, _dp]),
     "ppmlr_set_inflow": (C.c_int, [_P, _dp]),
     "ppmlr_set_inner": (C.c_int, [_P, C.c_double, C.c_double]),
+    "ppmlr_iono_default_params": (None, [C.POINTER(IonoParams)]),
+    "ppmlr_ionosphere_couple": (C.c_int, [_P, C.POINTER(State), C.POINTER(IonoParams), C.c_void_p, C.c_void_p]),
+    "ppmlr_ionosphere_detach": (C.c_int, [_P]),
     "ppmlr_sweep": (C.c_int, [_P, C.POINTER(State), C.c_double, C.c_int]),
     "ppmlr_step": (C.c_int, [_P, C.POINTER(State), C.c_double]),
     "ppmlr_set_step_index": (C.c_int, [_P, C.c_longlong]),
@@ -161,6 +174,12 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def iono_default_params() -> IonoParams:
+    p = IonoParams()
+    lib().ppmlr_iono_default_params(C.byref(p))
+    return p
 
 
 def default_options() -> Options:
@@ -252,6 +271,33 @@ class Context:
 
     def set_inner(self, rho, p):
         return self._chk(lib().ppmlr_set_inner(self.h, float(rho), float(p)))
+
+    def ionosphere_couple(self, u, params: IonoParams | None = None, jr=None, phi=None, stream=None, **over):
+        """One ionosphere coupling of state u (see ppmlr_ionosphere_couple):
+        the context keeps the drift of the reset zones for later sweeps.  jr,
+        phi: optional device float64 tensors [2, n_theta, n_phi] receiving the
+        shell current and potential."""
+        prm = params if params is not None else iono_default_params()
+        known = {f[0] for f in IonoParams._fields_}
+        for k, v in over.items():
+            if k not in known:
+                raise TypeError(f"unknown ionosphere parameter {k!r}")
+            setattr(prm, k, v)
+        shape = (2, prm.n_theta, prm.n_phi)
+        ptrs = []
+        for t in (jr, phi):
+            if t is None:
+                ptrs.append(None)
+                continue
+            import torch
+            if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape:
+                raise ValueError(f"ionosphere outputs are contiguous device float64 tensors {shape}")
+            ptrs.append(C.c_void_p(t.data_ptr()))
+        st = self._st(u, stream)
+        return self._chk(lib().ppmlr_ionosphere_couple(self.h, C.byref(st), C.byref(prm), ptrs[0], ptrs[1]))
+
+    def ionosphere_detach(self):
+        return self._chk(lib().ppmlr_ionosphere_detach(self.h))
 
     def sweep(self, u, dt, axis, stream=None):
         st = self._st(u, stream)

@@ -1,6 +1,7 @@
 """Host logic of bench.py (no GPU): the single-GPU guard, the kernel source
 hash that decides whether the committed counter summary still describes the
-kernels, and the traffic figures taken from that summary only on a match."""
+sweep kernel (its source and the headers it includes), and the traffic
+figures taken from that summary only on a match."""
 import json
 import os
 import shutil
@@ -14,7 +15,7 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 SOURCES = ("paper_1607_02214_amd/csrc/ppmlr_sweep.hpp", "paper_1607_02214_amd/csrc/ppmlr_mlp.hpp",
-           "paper_1607_02214_amd/csrc/ppmlr_lib.hip")
+           "paper_1607_02214_amd/csrc/ppmlr_char.hpp")
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
