@@ -118,8 +118,10 @@ def test_precision_study_512x384x384():
     GC.log(f"[fullsize] FP32 vs FP64 GPU after {k} steps: {err}; totals drift rho/E' {drift}")
     assert all(v <= 1e-5 for v in drift.values()), drift
     # pointwise FP32 error grows at limiter flips and shocks; the normwise
-    # bound is stated per field
+    # bound is stated per field (R24 metric; the momentum against the flow's
+    # momentum scale)
     assert err["rho"] <= 1e-3 and err["p"] <= 1e-3, err
+    assert err["|B'|"] <= 1e-3 and err["m"] <= 1e-3, err
     # FP64 GPU vs FP64 oracle on the 64^3 subvolume starting at the cell
     # that contains (8, -4, -4) R_E, evolved as an extended block
     cell = [int(np.searchsorted(setup.faces[a], c) - 1) for a, c in enumerate((8.0, -4.0, -4.0))]
@@ -140,6 +142,7 @@ def test_precision_study_512x384x384():
     assert np.all(e <= 1e-10), e
     e32 = GC.fp32_errors(U32[:, cell[2]:cell[2] + 64, cell[1]:cell[1] + 64, cell[0]:cell[0] + 64], ref)
     GC.log(f"[fullsize] FP32 GPU vs oracle on the 64^3 subvolume: {e32}")
+    assert all(v <= 1e-3 for v in e32.values()), e32
 
 
 @pytest.mark.timeout(600)
