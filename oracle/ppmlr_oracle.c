@@ -47,13 +47,13 @@
  * stretched grids, inner mask); the totals against closed-form volume
  * integrals of linear fields; the Alfven pair with unequal densities against
  * the two-medium jump conditions; the factor 2 of the Eq. 1.8 limiter (a
- * clipped linear profile reaches the neighbouring average).
- *
- * Parity unpinned (no check sees them): the time-centring term
- * B'_n dB_d,t/dm (its effect stays below the truncation error of every
- * convergence pin), the numerical values of the flattening constants (only
- * the on/off behaviour and its direction are pinned) and the P >= P0/2 clamp
- * of the coupled traced pressure (never active in the pins).
+ * clipped linear profile reaches the neighbouring average); the
+ * time-centring terms B'_n dB_d/dm of the split step (a plasma at rest on a
+ * pencil through the dipole against the exact second-order Taylor expansion
+ * of its transverse field, both tracing modes); the flattening constants
+ * (measured from outside with compressive steps against the published
+ * CW84 values); the P >= P0/2 bound on the coupled traced pressure (active
+ * in a low-beta shear, which stays positive and converged only with it).
  */
 #include <math.h>
 #include <stdlib.h>

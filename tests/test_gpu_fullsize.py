@@ -118,8 +118,8 @@ def test_precision_study_512x384x384():
     GC.log(f"[fullsize] FP32 vs FP64 GPU after {k} steps: {err}; totals drift rho/E' {drift}")
     assert all(v <= 1e-5 for v in drift.values()), drift
     # pointwise FP32 error grows at limiter flips and shocks; the normwise
-    # bound is stated per field (R24 metric; the momentum against the flow's
-    # momentum scale)
+    # bound is stated per field (max error over the field's largest value;
+    # the momentum against the flow's momentum scale)
     assert err["rho"] <= 1e-3 and err["p"] <= 1e-3, err
     assert err["|B'|"] <= 1e-3 and err["m"] <= 1e-3, err
     # FP64 GPU vs FP64 oracle on the 64^3 subvolume starting at the cell

@@ -1,6 +1,6 @@
 """Pins of oracle functions that the scheme-level pins do not reach.
 
-* `cfl_dt` (reading R18 of the split step: dt = CFL / max over unmasked zones
+* `cfl_dt` (the split step's time step: dt = CFL / max over unmasked zones
   of max_a (|v_a| + c_f,a) / dx_a with the total field) against the largest
   eigenvalue magnitude of the 1D ideal-MHD Jacobian along each axis, taken
   numerically with `numpy.linalg.eigvals`, on anisotropic states on

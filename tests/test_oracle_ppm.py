@@ -172,3 +172,52 @@ def test_parabolas_with_full_flattening_are_constant():
     par = O.ppm_parabolas(a, w, flat=np.ones(20))
     assert np.allclose(par[0, 2:18], a[2:18], rtol=0, atol=1e-15)
     assert np.allclose(par[1:, 2:18], 0.0, atol=1e-15)
+
+
+def test_flattening_constants_measured_from_outside_match_cw84():
+    # Colella & Woodward (1984), appendix, give the shock detector's constants
+    # as epsilon = 0.33 (relative pressure jump that counts as a shock),
+    # omega1 = 0.75 and omega2 = 10 (the coefficient rises from 0 to 1 as the
+    # ratio of the 2-zone to the 4-zone pressure difference goes from omega1
+    # to omega1 + 1/omega2).  The oracle is probed as a black box with
+    # compressive steps, and the three numbers are measured from its output.
+    M, j = 15, 7
+    i = np.arange(M)
+    un = np.where(i < j, 1.0, 0.0)
+
+    def step(PL, D, w):
+        return PL + D * 0.5 * (1.0 + np.tanh((i - j) / w))
+
+    # epsilon: a sharp step (ratio ~1, full flattening once detected); the
+    # jump at which the coefficient turns on, relative to the lower pressure
+    PL, lo, hi = 2.0, 0.1, 1.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        Pt = step(PL, mid * PL, 0.05)
+        if np.max(O.flattening(Pt, Pt, un)) > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    assert abs(hi - 0.33) < 1e-12, hi
+    # omega1, omega2: steps of growing width lower the central ratio
+    # r = (P_{j+1} - P_{j-1}) / (P_{j+2} - P_{j-2}); the coefficient's peak
+    # against r is a ramp whose zero and slope are the constants
+    rs, fs = [], []
+    for w in np.linspace(0.3, 1.2, 40):
+        Pt = step(PL, 3.0 * PL, w)
+        rs.append((Pt[j + 1] - Pt[j - 1]) / (Pt[j + 2] - Pt[j - 2]))
+        fs.append(np.max(O.flattening(Pt, Pt, un)))
+    rs, fs = np.array(rs), np.array(fs)
+    ramp = (fs > 0.0) & (fs < 1.0)
+    assert ramp.sum() >= 8
+    k, c = np.polyfit(rs[ramp], fs[ramp], 1)
+    assert abs(k - 10.0) < 1e-9 and abs(-c / k - 0.75) < 1e-12, (k, -c / k)
+    assert np.all(fs[rs <= 0.75] == 0.0) and np.all(fs[rs >= 0.85] == 1.0)
+    # the coefficient of the steepest zone spreads one zone to the side of
+    # the higher pressure (CW84: f_j takes the larger of its own and its
+    # lower-pressure neighbour's), and the mirror image mirrors it
+    Pt = step(PL, 3.0 * PL, 0.95)
+    f = O.flattening(Pt, Pt, un)
+    assert 0.0 < f[j] < 1.0 and f[j + 1] == f[j] and f[j - 1] == 0.0
+    fm = O.flattening(Pt[::-1].copy(), Pt[::-1].copy(), -un[::-1].copy())
+    assert np.array_equal(fm, f[::-1])
