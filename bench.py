@@ -397,6 +397,26 @@ def ensemble_leg(args):
         forms[name] = {"ms_per_step": e0.elapsed_time(e1) / 10,
                        "value": zones * 10 / (e0.elapsed_time(e1) / 1000.0)}
         del ws, cx
+    # the same members run one after another, each with its own single-run
+    # launches (device-resident dt loop, the same segments, the automatic
+    # tile): what the batched launches replace
+    cx = [member_ctx(st) for st in setups]
+    for c, c0 in zip(cx, ctxs):
+        for a in range(3):
+            c.set_segments(a, c0.get_segments(a))
+    ws = [u.clone() for u in us]
+    for c, w in zip(cx, ws):
+        c.advance(w, 1, args.cfl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c, w in zip(cx, ws):
+        c.advance(w, 10, args.cfl)
+    e1.record()
+    torch.cuda.synchronize()
+    forms["solo_sequential"] = {"ms_per_step": e0.elapsed_time(e1) / 10,
+                                "value": zones * 10 / (e0.elapsed_time(e1) / 1000.0)}
+    del ws, cx
     ppmlr.set_ensemble_launch(ppmlr.ENSEMBLE_PER_SWEEP)
     ppmlr.ensemble_run(ctxs, us, 2, args.cfl)
     torch.cuda.synchronize()
