@@ -77,6 +77,19 @@ def load_traffic(dtype: str):
     return d, d.get("source_hash")
 
 
+def shape_record(prof, axis, shape):
+    """The record of a committed counter summary taken with the tile shape
+    `shape` = (pencils per workgroup, segments, segment order) on `axis`: the
+    summary's own shape or one of its alternates; None if none matches (its
+    bytes and instruction counts then describe other launches)."""
+    if not prof:
+        return None
+    for rec in [prof] + list(prof.get("alternates", [])):
+        if (rec["tiles"][axis], rec["segments"][axis], rec["segment_order"][axis]) == tuple(shape):
+            return rec
+    return None
+
+
 def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
     """FP64 oracle on a bounded sample of pencils of the same state (all three
     sweep directions, equal pencil counts), timed on the host cores."""
@@ -552,6 +565,9 @@ def main():
                     help="pencils per tile x,y,z for the FP32 run (with --segments: no autotuning)")
     ap.add_argument("--segments", type=str, default=None, help="segments per pencil x,y,z for the FP32 run")
     ap.add_argument("--order", type=str, default=None, help="segment tile order x,y,z (1 adjacent, 2 bands) with --tiles")
+    ap.add_argument("--tiles64", type=str, default=None, help="pencils per workgroup x,y,z for the FP64 run")
+    ap.add_argument("--segments64", type=str, default=None, help="segments per pencil x,y,z for the FP64 run")
+    ap.add_argument("--order64", type=str, default=None, help="segment tile order x,y,z for the FP64 run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -695,18 +711,17 @@ def main():
     # on that axis; the counts do not depend on the box), over the live launch
     # time
     issue = None
-    shape_now = (ctx.get_tile(dom, ppmlr.F32), ctx.get_segments(dom), ctx.get_segment_order(dom))
-    if traffic and "valu_instructions_per_launch" in traffic:
-        shape_then = (traffic["tiles"][dom], traffic["segments"][dom], traffic["segment_order"][dom])
-        if shape_then == shape_now:
-            valu = traffic["valu_instructions_per_launch"][str(dom)]
-            trans = traffic["trans_instructions_per_launch"][str(dom)]
-            rate = valu / (avg[dom] / 1000.0) / 1e9
-            cyc = (valu + trans) / (avg[dom] / 1000.0) / 1e9
-            issue = {"achieved": round(rate, 1), "peak": VALU_ISSUE_PEAK_G, "unit": "G wave64 VALU instructions/s",
-                     "frac": round(rate / VALU_ISSUE_PEAK_G, 4),
-                     "frac_transcendentals_at_half_rate": round(cyc / VALU_ISSUE_PEAK_G, 4),
-                     "valu_per_launch": valu, "source": "committed counter summary, live launch time"}
+    rec = shape_record(traffic, dom, (ctx.get_tile(dom, ppmlr.F32), ctx.get_segments(dom),
+                                      ctx.get_segment_order(dom)))
+    if rec and "valu_instructions_per_launch" in rec:
+        valu = rec["valu_instructions_per_launch"][str(dom)]
+        trans = rec["trans_instructions_per_launch"][str(dom)]
+        rate = valu / (avg[dom] / 1000.0) / 1e9
+        cyc = (valu + trans) / (avg[dom] / 1000.0) / 1e9
+        issue = {"achieved": round(rate, 1), "peak": VALU_ISSUE_PEAK_G, "unit": "G wave64 VALU instructions/s",
+                 "frac": round(rate / VALU_ISSUE_PEAK_G, 4),
+                 "frac_transcendentals_at_half_rate": round(cyc / VALU_ISSUE_PEAK_G, 4),
+                 "valu_per_launch": valu, "source": "committed counter summary, live launch time"}
     tflops = flops_zone * zones / (avg[dom] / 1000.0) / 1e12
     roofline = {
         "bound": "hbm",
@@ -714,7 +729,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(gbs / HBM_PEAK_GBS, 4),
-        "traffic": traffic["bytes_per_launch"][str(dom)] if traffic else None,
+        "traffic": rec["bytes_per_launch"][str(dom)] if rec else None,
         "kernel": f"sweep axis {'xyz'[dom]} (f32)",
         "bytes_per_zone_sweep": 64,
         "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -785,17 +800,28 @@ def main():
     if not args.no_fp64:
         n64 = max(5, min(20, args.steps))
         print(f"[bench] fp64 plain: {n64} steps", file=sys.stderr, flush=True)
-        ctx64, u64, ms64, _, kms64, kn64, status64, _, fin64 = run(torch.float64, n64, 2)
+        shape64 = None
+        if args.tiles64 or args.segments64:
+            if not (args.tiles64 and args.segments64):
+                raise SystemExit("--tiles64 and --segments64 go together")
+            shape64 = ([int(x) for x in args.tiles64.split(",")], [int(x) for x in args.segments64.split(",")],
+                       [int(x) for x in args.order64.split(",")] if args.order64 else None)
+        ctx64, u64, ms64, _, kms64, kn64, status64, _, fin64 = run(torch.float64, n64, 2, shape=shape64)
         v64 = zones * n64 / (ms64 / 1000.0)
         avg64 = [kms64[a] / kn64[a] if kn64[a] else 0.0 for a in range(3)]
         d64 = int(np.argmax(avg64))
         ach64 = 128.0 * zones / (avg64[d64] / 1000.0) / 1e9
         traffic64, _ = load_traffic("f64")
+        sh64 = [(ctx64.get_tile(a, ppmlr.F64), ctx64.get_segments(a, ppmlr.F64), ctx64.get_segment_order(a))
+                for a in range(3)]
+        rec64 = shape_record(traffic64, d64, sh64[d64])
         out["fp64_plain"] = {"value": v64, "steps": n64, "ms_per_step": ms64 / n64,
                              "roofline_frac": round(ach64 / HBM_PEAK_GBS, 4),
                              "dominant_kernel": f"sweep axis {'xyz'[d64]} (f64)",
                              "avg_launch_ms": [round(a, 4) for a in avg64],
-                             "traffic": traffic64["bytes_per_launch"][str(d64)] if traffic64 else None,
+                             "tiles": [x[0] for x in sh64], "segments": [x[1] for x in sh64],
+                             "segment_order": [x[2] for x in sh64],
+                             "traffic": rec64["bytes_per_launch"][str(d64)] if rec64 else None,
                              "status": status64, "finite": fin64, "fp32_speedup": value / v64}
         del u64
         torch.cuda.empty_cache()

@@ -60,3 +60,14 @@ def test_traffic_summary_used_only_for_the_source_it_was_taken_from(source_copy,
     rec["source_hash"] = "0" * 16                                # taken from other sources
     (prof / "traffic_sweep_inflow_dipole_f32.json").write_text(json.dumps(rec))
     assert bench.load_traffic("f32") == (None, "0" * 16)
+
+
+def test_counter_record_matches_the_launched_tile_shape():
+    prof = {"tiles": [5, 8, 8], "segments": [3, 4, 4], "segment_order": [1, 1, 2], "bytes_per_launch": {"2": 1.0},
+            "alternates": [{"tiles": [5, 4, 4], "segments": [3, 4, 4], "segment_order": [1, 2, 2],
+                            "bytes_per_launch": {"2": 2.0}}]}
+    assert bench.shape_record(prof, 2, (8, 4, 2))["bytes_per_launch"]["2"] == 1.0
+    assert bench.shape_record(prof, 2, (4, 4, 2))["bytes_per_launch"]["2"] == 2.0
+    assert bench.shape_record(prof, 2, (4, 4, 1)) is None          # other tile order
+    assert bench.shape_record(prof, 1, (8, 4, 2)) is None          # y was taken with order 1 or 2, not this
+    assert bench.shape_record(None, 2, (8, 4, 2)) is None
