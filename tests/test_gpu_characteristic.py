@@ -135,6 +135,50 @@ def test_fp32_against_fp64_oracle():
         assert all(v <= 2e-5 for v in err.values()), (case.name, err)
 
 
+
+@pytest.mark.timeout(600)
+def test_bench_workload_sampled_pencils_fp32():
+    # The benchmark's inflow-dipole grid (256 x 192 x 192, FP32, automatic
+    # tiles, device dt loop) in the characteristic mode: 5 steps, then one
+    # sweep per axis; sampled pencils (and the pencils through the middle:
+    # dipole, inner boundary, bow shock) against the oracle's characteristic
+    # mode on the same FP32-rounded input, pencil by pencil.
+    from oracle import oracle as O
+    from paper_1607_02214_amd import inputs as I
+    from paper_1607_02214_amd import ppmlr
+    setup = I.c2_setup()
+    n = [len(f) - 1 for f in setup.faces]
+    GC.log(f"[char] inflow-dipole {n} fp32: 5 steps, one sweep per axis")
+    ctx = ppmlr.Context(setup.faces, setup.bc_lo, setup.bc_hi, r_inner=setup.r_inner, p_floor=setup.p_floor,
+                        tracing=1)
+    ctx.set_dipole(setup.moment, setup.direction)
+    ctx.set_inflow(setup.inflow)
+    ctx.set_inner(setup.inner_rho, setup.inner_p)
+    u = _dev(setup.U, torch.float32)
+    ctx.advance(u, 5, 0.4)
+    ora = O.OracleProblem(setup.faces, bc_lo=setup.bc_lo, bc_hi=setup.bc_hi, dip_moment=setup.moment,
+                          dip_dir=setup.direction, inflow=setup.inflow, r_inner=setup.r_inner,
+                          inner_rho=setup.inner_rho, inner_p=setup.inner_p, p_floor=setup.p_floor, tracing=1)
+    rng = np.random.default_rng(77)
+    for axis in range(3):
+        Uin = _host(u)
+        dt = ctx.cfl_dt(u, 0.4)
+        ctx.sweep(u, dt, axis)
+        out = _host(u)
+        n1, n2 = n[(axis + 1) % 3], n[(axis + 2) % 3]
+        j1 = np.concatenate([rng.integers(0, n1, 32), [n1 // 2, n1 // 2 - 1, n1 // 2]])
+        j2 = np.concatenate([rng.integers(0, n2, 32), [n2 // 2, n2 // 2, n2 // 2 - 1]])
+        ref = ora.sweep_pencils(Uin, dt, axis, j1, j2)
+        got = np.empty_like(ref)
+        for q in range(len(j1)):
+            idx = [slice(None)] * 3
+            idx[2 - (axis + 1) % 3] = j1[q]
+            idx[2 - (axis + 2) % 3] = j2[q]
+            got[q] = out[(slice(None),) + tuple(idx)]
+        err = GC.fp32_errors(got.transpose(1, 0, 2).reshape(8, -1), ref.transpose(1, 0, 2).reshape(8, -1))
+        GC.log(f"[char] bench workload axis {axis} fp32 vs oracle on {len(j1)} pencils: {err}")
+        assert all(v <= 2e-5 for v in err.values()), (axis, err)
+
 def test_modes_that_do_not_take_the_characteristic_mode_are_refused():
     from paper_1607_02214_amd import inputs as I
     from paper_1607_02214_amd import ppmlr

@@ -170,3 +170,64 @@ def test_refusals():
     with pytest.raises(ppmlr.PPMLRError) as ei:
         c2.ionosphere_couple(u)
     assert ei.value.status == ppmlr.PPMLR_EINVAL and "dipole" in str(ei.value)
+
+
+@pytest.mark.timeout(600)
+def test_coupling_on_the_bench_workload():
+    # The benchmark's inflow-dipole run (256 x 192 x 192, FP32, device dt
+    # loop) after 10 steps: the shell current and potential at the default
+    # shell against the oracle on the same FP32 state, then one x sweep of
+    # pencils through the reset zones against the oracle's sweep with the
+    # oracle's drift.  The oracle's coupling reads the block of zones that
+    # holds every zone the current's stencils touch around the r_fac sphere
+    # (3 zones of margin): its differences are zone-local, so the block gives
+    # the whole grid's values there.
+    from oracle import oracle as O
+    from oracle import ionosphere as IO
+    from paper_1607_02214_amd import ppmlr
+    setup = I.c2_setup()
+    n = [len(f) - 1 for f in setup.faces]
+    GC.log(f"[iono] bench workload {n} fp32: 10 steps, coupling, one x sweep")
+    ctx = ppmlr.Context(setup.faces, setup.bc_lo, setup.bc_hi, r_inner=setup.r_inner, p_floor=setup.p_floor)
+    ctx.set_dipole(setup.moment, setup.direction)
+    ctx.set_inflow(setup.inflow)
+    ctx.set_inner(setup.inner_rho, setup.inner_p)
+    u = _dev(setup.U, torch.float32)
+    ctx.advance(u, 10, 0.4)
+    prm = ppmlr.iono_default_params()
+    jr = torch.zeros((2, prm.n_theta, prm.n_phi), dtype=torch.float64, device="cuda")
+    phi = torch.zeros_like(jr)
+    ctx.ionosphere_couple(u, prm, jr=jr, phi=phi)
+    U = _host(u)
+    cs = IO.centres(setup.faces)
+    lo = [max(0, int(np.searchsorted(c, -prm.r_fac)) - 3) for c in cs]
+    hi = [min(len(c), int(np.searchsorted(c, prm.r_fac)) + 3) for c in cs]
+    sub = [np.asarray(setup.faces[a])[lo[a]:hi[a] + 1] for a in range(3)]
+    Us = np.ascontiguousarray(U[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+    grid = IO.ShellGrid(prm.n_theta, prm.n_phi, r_shell=prm.r_shell, r_fac=prm.r_fac)
+    jr_o = IO.shell_current(sub, Us, setup.moment, list(setup.direction), grid)
+    phi_o = IO.solve_potential(grid, jr_o, prm.sigma)
+    box, v_o = IO.inner_drift(sub, setup.r_inner, setup.moment, list(setup.direction), grid, phi_o)
+    e_jr = float(np.max(np.abs(_host(jr) - jr_o)) / np.max(np.abs(jr_o)))
+    e_phi = float(np.max(np.abs(_host(phi) - phi_o)) / np.max(np.abs(phi_o)))
+    GC.log(f"[iono] bench workload: max|jr| {np.max(np.abs(jr_o)):.3e}, jr {e_jr:.2e}, phi {e_phi:.2e}")
+    assert np.max(np.abs(jr_o)) > 0 and np.max(np.abs(v_o)) > 0
+    assert e_jr <= 1e-12, e_jr
+    assert e_phi <= 1e-11, e_phi
+    ora = O.OracleProblem(setup.faces, bc_lo=setup.bc_lo, bc_hi=setup.bc_hi, dip_moment=setup.moment,
+                          dip_dir=setup.direction, inflow=setup.inflow, r_inner=setup.r_inner,
+                          inner_rho=setup.inner_rho, inner_p=setup.inner_p, p_floor=setup.p_floor)
+    full = (box[0] + lo[0], box[1] + lo[0], box[2] + lo[1], box[3] + lo[1], box[4] + lo[2], box[5] + lo[2])
+    ora.set_inner_velocity(full, v_o)
+    dt = ctx.cfl_dt(u, 0.4)
+    ctx.sweep(u, dt, 0)
+    out = _host(u)
+    ys = np.linspace(full[2], full[3] - 1, 5).astype(int)
+    zs = np.linspace(full[4], full[5] - 1, 5).astype(int)
+    j1 = np.repeat(ys, len(zs))
+    j2 = np.tile(zs, len(ys))
+    ref = ora.sweep_pencils(U, dt, 0, j1, j2)
+    got = np.stack([out[:, j2[p], j1[p], :] for p in range(len(j1))])
+    err = GC.fp32_errors(got.transpose(1, 0, 2).reshape(8, -1), ref.transpose(1, 0, 2).reshape(8, -1))
+    GC.log(f"[iono] bench workload: coupled x sweep of {len(j1)} pencils through the reset zones: {err}")
+    assert all(val <= 2e-5 for val in err.values()), err
