@@ -1,6 +1,6 @@
 """The instrumented (operation-counting) build of the oracle computes what
 the oracle computes, bit for bit, and the benchmark's operation count per
-zone-sweep is the one this build gives on the stated sample."""
+zone-sweep is the one the counting oracle gives on the stated sample."""
 import importlib.util
 import os
 
