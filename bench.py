@@ -236,6 +236,54 @@ def ionosphere_leg(args, setup, make_ctx, shape_ctx, u_dev):
             "status": ctx.status_check(), "finite": bool(torch.isfinite(u).all().item())}
 
 
+def characteristic_leg(args, setup, make_ctx, value_plain, fp64=True):
+    """The FP32 run in the characteristic mode (the seven waves traced one by
+    one and the linearised seven-wave interface problem) from the same start
+    state: its own tile search after the warm-up steps (3 repetitions per
+    candidate), then args.steps timed steps with per-sweep launch times; and
+    its error against the FP64 characteristic run of the same steps."""
+    import numpy as np
+    import torch
+    from paper_1607_02214_amd import ppmlr
+
+    ctx = make_ctx(tracing=ppmlr.TRACE_CHARACTERISTIC)
+    u = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float32).contiguous()
+    ctx.advance(u, args.warmup, args.cfl)
+    torch.cuda.synchronize()
+    ctx.autotune(u, reps=3)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ctx.advance(u, args.steps, args.cfl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kms, kn = ctx.kernel_times()
+    zones = int(np.prod(setup.U.shape[1:]))
+    value = zones * args.steps / (ms / 1000.0)
+    avg = [kms[a] / kn[a] if kn[a] else 0.0 for a in range(3)]
+    dom = int(np.argmax(avg))
+    out = {"value": value, "unit": "zone-updates/s", "steps": args.steps, "ms_per_step": ms / args.steps,
+           "speedup_vs_fp32_plain": value / value_plain,
+           "roofline_frac": round(64.0 * zones / (avg[dom] / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+           "dominant_kernel": f"sweep axis {'xyz'[dom]} (f32, characteristic)",
+           "tiles": [ctx.get_tile(a) for a in range(3)], "segments": [ctx.get_segments(a) for a in range(3)],
+           "segment_order": [ctx.get_segment_order(a) for a in range(3)],
+           "avg_launch_ms": [round(a, 4) for a in avg],
+           "status": ctx.status_check(), "finite": bool(torch.isfinite(u).all().item()),
+           "simulated_time": ctx.time(u)}
+    if fp64:
+        ctx64 = make_ctx(tracing=ppmlr.TRACE_CHARACTERISTIC)
+        u64 = torch.from_numpy(setup.U).to(device="cuda", dtype=torch.float64).contiguous()
+        ctx64.advance(u64, args.warmup + args.steps, args.cfl)
+        torch.cuda.synchronize()
+        out["fp32_vs_fp64"] = fp32_vs_fp64(ctx, u, ctx64, u64)
+        out["fp32_vs_fp64"]["after_steps"] = args.warmup + args.steps
+        del u64
+    return out
+
+
 def learned_leg(args, setup, make_ctx, u_plain, st_plain, value_plain, ref64=None):
     """The learned Riemann guess on the same workload: harvest interface
     records from a plain FP32 run of the start state, train the network on
@@ -554,6 +602,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-series", action="store_true")
     ap.add_argument("--no-iono", action="store_true", help="skip the ionosphere coupling leg")
+    ap.add_argument("--no-char", action="store_true", help="skip the characteristic-mode leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 512x384x384 leg")
     ap.add_argument("--c3-steps", type=int, default=20)
     ap.add_argument("--harvest-steps", type=int, default=105,
@@ -588,8 +637,9 @@ def main():
     zones = nx * ny * nz
     print(f"[bench] grid {nx}x{ny}x{nz} = {zones} zones, building state", file=sys.stderr, flush=True)
 
-    def make_ctx():
-        ctx = ppmlr.Context(setup.faces, setup.bc_lo, setup.bc_hi, r_inner=setup.r_inner, p_floor=setup.p_floor)
+    def make_ctx(**over):
+        ctx = ppmlr.Context(setup.faces, setup.bc_lo, setup.bc_hi, r_inner=setup.r_inner, p_floor=setup.p_floor,
+                            **over)
         ctx.set_dipole(setup.moment, setup.direction)
         ctx.set_inflow(setup.inflow)
         ctx.set_inner(setup.inner_rho, setup.inner_p)
@@ -787,6 +837,10 @@ def main():
     if not args.no_iono:
         print("[bench] ionosphere coupling", file=sys.stderr, flush=True)
         out["ionosphere"] = ionosphere_leg(args, setup, make_ctx, ctx, u)
+        torch.cuda.empty_cache()
+    if not args.no_char:
+        print("[bench] characteristic mode", file=sys.stderr, flush=True)
+        out["characteristic"] = characteristic_leg(args, setup, make_ctx, value, fp64=not args.no_fp64)
         torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned"] = learned_leg(args, setup, make_ctx, u, st, value,
