@@ -4,7 +4,9 @@
    tiles, device-resident dt loop): after a few steps, one sweep per axis;
    sampled pencils are compared with the FP64 oracle applied to the same
    (FP32-rounded) input, pencil by pencil.
-2. The precision study on the 512x384x384 grid (every cell of the bench grid
+2. The same grid in FP64, whole: one split step with a time-dependent
+   inflow against the oracle's step of every zone.
+3. The precision study on the 512x384x384 grid (every cell of the bench grid
    split in two): FP32 GPU run against an FP64 GPU run (per-field error and
    drift of the conserved totals), and the FP64 GPU run against the FP64
    oracle on a 64^3 subvolume.  The subvolume is evolved by the oracle as an
@@ -83,6 +85,34 @@ def test_bench_workload_sampled_pencils_fp32():
         GC.log(f"[fullsize] axis {axis} tiles {tiles} fp32 vs oracle on {len(j1)} pencils: {err}")
         assert all(v <= 2e-5 for v in err.values()), (axis, err)
 
+
+
+@pytest.mark.timeout(900)
+def test_full_grid_fp64_step_with_inflow_series():
+    # Every zone of the benchmark grid (256 x 192 x 192, FP64, stretched,
+    # dipole, inner boundary) after one split step whose inflow ghosts hold
+    # a time-dependent solar wind (the series at the step's mid-time),
+    # against the oracle's step of the whole grid (~15-30 s on the host).
+    from oracle import oracle as O
+    setup = I.c2_setup()
+    n = [len(f) - 1 for f in setup.faces]
+    GC.log(f"[fullsize] whole grid {n} fp64: one step with an inflow series against the oracle")
+    ora = _oracle(setup)
+    dt = ora.cfl_dt(setup.U, 0.4)
+    times, prims = I.solar_wind_series(10 * dt, n_knots=5, seed=12)
+    ctx = _ctx(setup)
+    ctx.set_inflow_series(times, prims)
+    u = torch.from_numpy(setup.U).to("cuda", torch.float64).contiguous()
+    ctx.step(u, dt)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    del u
+    ref = O.step_with_series(ora, setup.U, dt, 0, 0.0, times, prims)
+    err = GC.normwise_errors(got, ref)
+    pt = GC.pointwise_errors(got, ref, by_family=True)
+    GC.log(f"[fullsize] whole grid fp64 step: normwise {err.max():.2e}, pointwise {pt.max():.2e}")
+    assert np.all(err <= 1e-11), err
+    assert np.all(pt <= 1e-7), pt
 
 def _subvolume(setup, lo, size):
     faces = [setup.faces[a][lo[a]:lo[a] + size[a] + 1] for a in range(3)]
