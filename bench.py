@@ -124,6 +124,14 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
         el += e
         chunks += 1
     threads = O.get_threads()
+    # one whole split step of the same state (every pencil of the three
+    # sweeps, the oracle's own whole-grid path), when the sampled rate puts
+    # it under ~8 s (the whole-grid path ran up to 3x slower than that)
+    el_step = None
+    if 3.0 * float(np.prod(n)) / (zs / el) < 8.0:
+        t0 = time.perf_counter()
+        prob.step(U, dt, 0)
+        el_step = time.perf_counter() - t0
     # the same sample kind on one core (bounded to ~5 s)
     O.set_threads(1)
     zs1, el1 = 0, 0.0
@@ -147,6 +155,9 @@ def cpu_baseline(setup, dt, seconds_target=15.0, seed=0):
         "kind": "oracle",
         "sample": f"{chunks} x 2048 random pencils per sweep direction of the 256x192x192 inflow-dipole start "
                   f"state ({zs} zone-sweeps, {el:.1f} s, FP64, OpenMP over pencils); zone-updates = zone-sweeps / 3",
+        "whole_step": None if el_step is None else {
+            "value": float(np.prod(n)) / el_step, "unit": "zone-updates/s", "cores": threads,
+            "sample": f"one whole split step of the {n[0]}x{n[1]}x{n[2]} start state ({el_step:.1f} s)"},
         "single_core": {"value": zs1 / el1 / 3.0, "unit": "zone-updates/s", "cores": 1,
                         "sample": f"128-pencil samples, {zs1} zone-sweeps, {el1:.1f} s"},
         "periodic_32cubed_full": {"value": 32 ** 3 * 20 / el_c1, "unit": "zone-updates/s", "cores": threads,
