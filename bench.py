@@ -841,22 +841,26 @@ def main():
         torch.cuda.synchronize()
         out["fp32_vs_fp64"] = fp32_vs_fp64(ctx, u, ctx_r, u_r)
         out["fp32_vs_fp64"]["after_steps"] = args.warmup + args.steps
+    def leg(name, fn, *a, **k):
+        # a secondary leg that fails reports its error in its own field and
+        # leaves the headline line standing
+        print(f"[bench] {name}", file=sys.stderr, flush=True)
+        try:
+            out[name] = fn(*a, **k)
+        except Exception as e:   # noqa: BLE001
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"[bench] {name} failed: {e}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
     if not args.no_series:
-        print("[bench] inflow time series", file=sys.stderr, flush=True)
-        out["inflow_series"] = series_leg(args, setup, make_ctx, ctx)
-        torch.cuda.empty_cache()
+        leg("inflow_series", series_leg, args, setup, make_ctx, ctx)
     if not args.no_iono:
-        print("[bench] ionosphere coupling", file=sys.stderr, flush=True)
-        out["ionosphere"] = ionosphere_leg(args, setup, make_ctx, ctx, u)
-        torch.cuda.empty_cache()
+        leg("ionosphere", ionosphere_leg, args, setup, make_ctx, ctx, u)
     if not args.no_char:
-        print("[bench] characteristic mode", file=sys.stderr, flush=True)
-        out["characteristic"] = characteristic_leg(args, setup, make_ctx, value, fp64=not args.no_fp64)
-        torch.cuda.empty_cache()
+        leg("characteristic", characteristic_leg, args, setup, make_ctx, value, fp64=not args.no_fp64)
     if not args.no_learned:
-        out["learned"] = learned_leg(args, setup, make_ctx, u, st, value,
-                                     ref64=None if args.no_fp64 else (ctx_r, u_r))
-        torch.cuda.empty_cache()
+        leg("learned", learned_leg, args, setup, make_ctx, u, st, value,
+            ref64=None if args.no_fp64 else (ctx_r, u_r))
     if not args.no_fp64:
         del u_r, ctx_r
     del u
@@ -892,8 +896,7 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_leg(args)
-        torch.cuda.empty_cache()
+        leg("ensemble", ensemble_leg, args)
 
     if not args.no_c3:
         def make_ctx_for(st):
@@ -902,16 +905,14 @@ def main():
             c.set_inflow(st.inflow)
             c.set_inner(st.inner_rho, st.inner_p)
             return c
-        out["c3_512x384x384"] = c3_leg(args, make_ctx_for)
-        torch.cuda.empty_cache()
+        leg("c3_512x384x384", c3_leg, args, make_ctx_for)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         prob = O.OracleProblem(setup.faces, bc_lo=setup.bc_lo, bc_hi=setup.bc_hi, dip_moment=setup.moment,
                                dip_dir=setup.direction, r_inner=setup.r_inner)
         dt = prob.cfl_dt(setup.U, args.cfl)
-        print(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(setup, dt, args.cpu_seconds)
+        leg("cpu_baseline", cpu_baseline, setup, dt, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
